@@ -1,0 +1,195 @@
+/*
+ * mclbm: moment-chain lattice Boltzmann method for hyperelastic solids on
+ * AMD Instinct MI355X (gfx950).  C ABI of the device library.
+ *
+ * The method (arXiv 2502.00920): a D2Q9 lattice (Tab. 1) carries the moment
+ * chain r, j, Pi of a solid in the reference configuration (Sect. 3.1); the
+ * part of the first Piola-Kirchhoff stress P(H) that the bare chain does not
+ * carry enters through the forcing term psi with the source
+ * S = rho0 b + Div(P(H) + Pi(H)) (Eq. source, Eq. forcing); BGK collision and
+ * streaming (Algorithm 1) run with modified bounce-back walls that prescribe a
+ * momentum j* (Eq. bbcon) and modified anti-bounce-back walls that prescribe a
+ * traction T* (Eq. abbcon, Sect. 3.3); the displacement follows from j by the
+ * trapezoidal rule (Sect. 3.2).  Materials: St. Venant-Kirchhoff and neo-Hooke
+ * (Sect. 4), plane strain; a linear-elastic material for tests.
+ *
+ * Units: the lattice velocity c = sqrt(3) c_s with c_s = sqrt(mu/rho0)
+ * (Sect. 3.2) and c = dX/dt (Sect. 2), so dt is derived from dx, mu and rho0;
+ * tau is dimensionless (relaxation time in units of dt).
+ *
+ * Memory: the caller owns all device memory.  mclbm_plan reports the arena
+ * size; the caller allocates it (e.g. torch.empty(bytes, dtype=uint8,
+ * device="cuda")) and hands it to mclbm_create together with a HIP stream.
+ * The library never allocates or frees device memory.  All work is enqueued on
+ * that stream; mclbm_read and mclbm_diag synchronise it.
+ *
+ * Fields exchanged with the caller are FP64, component-major, x fastest:
+ * [comp][ny][nx].  Node (i, k) sits at X = ((i + 1/2) dx, (k + 1/2) dx); the
+ * walls lie half way beyond the outermost nodes.
+ *
+ * Errors: every int function returns MCLBM_OK (0) or a negative status;
+ * mclbm_last_error() gives a message for the calling thread.  A handle is not
+ * thread safe; distinct handles may be used from distinct threads.
+ */
+#ifndef MCLBM_H
+#define MCLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum mclbm_status {
+    MCLBM_OK = 0,
+    MCLBM_EINVAL = -1,    /* invalid argument or parameter                      */
+    MCLBM_ETOOSMALL = -2, /* arena smaller than mclbm_plan reported             */
+    MCLBM_EHIP = -3,      /* a HIP runtime call failed (message has the detail) */
+    MCLBM_EUNSTABLE = -4, /* non-finite values found by mclbm_diag              */
+    MCLBM_ESTATE = -5     /* call out of order (e.g. step before init)          */
+};
+
+enum mclbm_material { MCLBM_SVK = 0, MCLBM_NEOHOOKE = 1, MCLBM_LINEAR = 2 };
+
+/* Storage and arithmetic of populations and stresses.  The displacement u is
+ * integrated in FP64 in every mode; the boundary momentum-flux assembly of
+ * Neumann walls is done in FP64 in every mode. */
+enum mclbm_precision { MCLBM_F64 = 0, MCLBM_F32 = 1 };
+
+enum mclbm_side { MCLBM_LEFT = 0, MCLBM_RIGHT = 1, MCLBM_BOTTOM = 2, MCLBM_TOP = 3 };
+
+/* Wall types (Sect. 3.3).  PERIODIC must be set on both opposite sides. */
+enum mclbm_bc { MCLBM_DIRICHLET = 0, MCLBM_NEUMANN = 1, MCLBM_PERIODIC = 2 };
+
+/* Time programs of a wall load, evaluated at the step index n (the step whose
+ * post-collision populations the wall reflects):
+ *   ZERO        0
+ *   CONST       amp
+ *   DISP_RAMP   Dirichlet only: a wall displacement amp reached at constant
+ *               speed over t1 steps and then held: j* = rho0 amp / (t1 dt)
+ *               for n < t1, else 0
+ *   LINEAR_RAMP amp * min(n / t1, 1)
+ *   SIN2_RAMP   amp * sin^2(pi n / (2 t1)) for n < t1, amp after (tension
+ *               load of Sect. 4.1 with the time in steps)
+ *   SIN_PULSE   amp * sin(pi n / t1) for n < t1, 0 after (shear momentum of
+ *               Sect. 4.2)
+ *   GAUSS       amp * exp(-(n - t0)^2 / (2 width^2)) for n <= t1, 0 after
+ *   RICKER      amp * 2/sqrt(3 width sqrt(pi)) (1 - (n-t0)^2/width)
+ *               * exp(-(n-t0)^2 / (2 width)) for n < t1, 0 after (Eq. of the
+ *               Ricker wavelet in Sect. 4.3, s = width, times in steps)
+ * For a Dirichlet wall the value is j* (momentum density), for a Neumann wall
+ * T* (traction, force per reference length). */
+enum mclbm_load_kind {
+    MCLBM_LOAD_ZERO = 0, MCLBM_LOAD_CONST = 1, MCLBM_LOAD_DISP_RAMP = 2,
+    MCLBM_LOAD_LINEAR_RAMP = 3, MCLBM_LOAD_SIN2_RAMP = 4, MCLBM_LOAD_SIN_PULSE = 5,
+    MCLBM_LOAD_GAUSS = 6, MCLBM_LOAD_RICKER = 7
+};
+
+/* Fields for mclbm_read, at t_n after n steps:
+ *   U  2 comps  displacement u_n
+ *   J  2        momentum j = sum_q c_q f_q + dt/2 S (the j of the collision
+ *               at t_n, Algorithm 1)
+ *   R  1        r = sum_q f_q
+ *   PI 3        Pi = sum_q c_q c_q f_q, (xx, xy, yy)
+ *   H  4        H = grad u by finite differences, (xx, xy, yx, yy),
+ *               H_ab = d u_a / d X_b
+ *   P  4        first Piola-Kirchhoff stress P(H), (xx, xy, yx, yy)
+ *   S  2        source S = rho0 b + Div(P(H) + Pi(H)) */
+enum mclbm_field {
+    MCLBM_FIELD_U = 0, MCLBM_FIELD_J = 1, MCLBM_FIELD_R = 2, MCLBM_FIELD_PI = 3,
+    MCLBM_FIELD_H = 4, MCLBM_FIELD_P = 5, MCLBM_FIELD_S = 6
+};
+
+typedef struct {
+    int32_t nx, ny;       /* lattice nodes, each >= 3                          */
+    int32_t material;     /* enum mclbm_material                                */
+    int32_t precision;    /* enum mclbm_precision                               */
+    double dx;            /* lattice spacing dX > 0                             */
+    double rho0;          /* reference density > 0                              */
+    double mu;            /* shear modulus > 0                                  */
+    double nu;            /* Poisson ratio in (-1, 0.5); lambda = 2 mu nu/(1-2nu)*/
+    double tau;           /* relaxation time in units of dt, > 0.5              */
+    double body[2];       /* body force b per unit mass                         */
+} mclbm_params;
+
+typedef struct {
+    int32_t bc;           /* enum mclbm_bc                                      */
+    int32_t kind;         /* enum mclbm_load_kind                               */
+    double amp[2];        /* load vector                                        */
+    double t0, t1, width; /* time-program parameters, in steps                  */
+} mclbm_side_spec;
+
+typedef struct {
+    int64_t step;         /* n                                                  */
+    double momentum[2];   /* sum_X sum_q c_q f_q(t_n)                           */
+    double ekin;          /* sum_X |j|^2 / (2 rho0), j as MCLBM_FIELD_J          */
+    double max_u;         /* max_X |u_n|                                        */
+    int32_t nonfinite;    /* 1 when any u or j is NaN or infinite               */
+} mclbm_diag_out;
+
+typedef struct mclbm_sim mclbm_sim; /* opaque host-side handle */
+
+/* Arena size for these parameters and the derived time step dt (either output
+ * pointer may be NULL).  Host only; validates the parameters.  Returns
+ * EINVAL for nx or ny < 3, dx, rho0 or mu <= 0, tau <= 0.5, nu outside
+ * (-1, 0.5) or unknown enums. */
+int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, double* dt_out);
+
+/* Create a simulation on the current HIP device inside the caller's arena
+ * (device pointer, at least mclbm_plan bytes, 256-byte aligned) and stream
+ * (a hipStream_t; NULL means the null stream).  Sides start as traction-free
+ * Neumann walls.  The arena and stream must outlive the handle; the handle
+ * owns no device memory.  Returns EINVAL, ETOOSMALL (arena too small or
+ * misaligned). */
+int mclbm_create(const mclbm_params* p, void* arena, size_t arena_bytes, void* stream,
+                 mclbm_sim** out);
+
+/* Wall program of one side (Sect. 3.3); allowed before every mclbm_init and
+ * between steps (the new program applies from the next step).  Periodic sides
+ * must be set in opposite pairs before mclbm_init.  Returns EINVAL for unknown
+ * enums, DISP_RAMP on a non-Dirichlet side, t1 <= 0 for programs that divide
+ * by it, or PERIODIC paired with a non-periodic side at init. */
+int mclbm_set_side(mclbm_sim* s, int side, const mclbm_side_spec* spec);
+
+/* Initial state (Algorithm 1, Initialise): u = u0 and populations at the
+ * equilibrium f_eq(r0 = -rho0 tr H(u0), j0, Pi(H(u0))).  u0 and j0 are
+ * [2][ny][nx] FP64 arrays on the host (on_device = 0) or the device
+ * (on_device = 1); NULL means zero.  Resets the step counter to 0. */
+int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, int on_device);
+
+/* Advance nsteps >= 0 time steps, enqueued asynchronously on the stream. */
+int mclbm_step(mclbm_sim* s, int64_t nsteps);
+
+/* Number of steps taken since mclbm_init. */
+int64_t mclbm_stepno(const mclbm_sim* s);
+
+/* Components of a field (see enum mclbm_field), 0 for an unknown field. */
+int mclbm_field_components(int field);
+
+/* Write one field at t_n into dst, FP64 [comp][ny][nx], on the host
+ * (on_device = 0) or the device (on_device = 1).  Synchronises the stream. */
+int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device);
+
+/* Global diagnostics at t_n (deterministic reductions on the device).
+ * Returns EUNSTABLE (with *out filled) when u or j hold non-finite values. */
+int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out);
+
+/* Checkpoints: the bytes of the state (populations, displacement, step
+ * counter) and copies of it to or from host / device memory.  A simulation
+ * loaded from a checkpoint continues bitwise as the one saved. */
+size_t mclbm_state_bytes(const mclbm_sim* s);
+int mclbm_save(mclbm_sim* s, void* dst, int on_device);
+int mclbm_load(mclbm_sim* s, const void* src, int on_device);
+
+/* Release the host handle (the arena stays with the caller). */
+int mclbm_destroy(mclbm_sim* s);
+
+/* Message of the last error on the calling thread ("" when none). */
+const char* mclbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCLBM_H */

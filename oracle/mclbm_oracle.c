@@ -187,18 +187,30 @@ void orc_stress_P(int material, double lam, double mu, const double H[4], double
             for (int b = 0; b < 2; b++)
                 S2[a][b] = (a == b ? lam * trE : 0.0) + 2.0 * mu * E[a][b];
     } else {
-        double C[2][2];
+        /* neo-Hooke: S = lam/2 (J^2 - 1) C^-1 + mu (I - C^-1)
+         *              = [lam/2 (J^2 - 1) I + mu (C - I)] C^-1,
+         * with C - I = H + H^T + H^T H and J^2 - 1 = (J - 1)(J + 1),
+         * J - 1 = tr H + det H, formed from H so that small strains keep
+         * their relative precision. */
+        double CmI[2][2], C[2][2];
         for (int a = 0; a < 2; a++)
-            for (int b = 0; b < 2; b++)
-                C[a][b] = F[0][a] * F[0][b] + F[1][a] * F[1][b];
-        double J = F[0][0] * F[1][1] - F[0][1] * F[1][0];
+            for (int b = 0; b < 2; b++) {
+                double HtH = Hm[0][a] * Hm[0][b] + Hm[1][a] * Hm[1][b];
+                CmI[a][b] = Hm[a][b] + Hm[b][a] + HtH;
+                C[a][b] = (a == b ? 1.0 : 0.0) + CmI[a][b];
+            }
+        double Jm1 = (Hm[0][0] + Hm[1][1]) + (Hm[0][0] * Hm[1][1] - Hm[0][1] * Hm[1][0]);
+        double J2m1 = Jm1 * (Jm1 + 2.0);
         double detC = C[0][0] * C[1][1] - C[0][1] * C[1][0];
         double Ci[2][2] = {{C[1][1] / detC, -C[0][1] / detC},
                            {-C[1][0] / detC, C[0][0] / detC}};
+        double A[2][2];
         for (int a = 0; a < 2; a++)
             for (int b = 0; b < 2; b++)
-                S2[a][b] = 0.5 * lam * (J * J - 1.0) * Ci[a][b] +
-                           mu * ((a == b ? 1.0 : 0.0) - Ci[a][b]);
+                A[a][b] = (a == b ? 0.5 * lam * J2m1 : 0.0) + mu * CmI[a][b];
+        for (int a = 0; a < 2; a++)
+            for (int b = 0; b < 2; b++)
+                S2[a][b] = A[a][0] * Ci[0][b] + A[a][1] * Ci[1][b];
     }
     for (int a = 0; a < 2; a++)
         for (int b = 0; b < 2; b++)

@@ -1,0 +1,424 @@
+// Host side of the mclbm C ABI: parameter validation, the arena layout, the wall
+// load programs and the launch sequence of the step.  No device allocation: the
+// caller provides the arena and the stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "mclbm.h"
+#include "mclbm_internal.hpp"
+
+#define MCLBM_EXPORT extern "C" __attribute__((visibility("default")))
+
+using namespace mclbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(MCLBM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int pitch;
+    size_t f_bytes, u_bytes, part_bytes, out_bytes;
+    size_t off_f[2], off_u[2], off_part, off_out, total;
+};
+
+Layout layout_of(const mclbm_params& p) {
+    Layout L;
+    L.pitch = (p.nx + 63) / 64 * 64;
+    const size_t elem = p.precision == MCLBM_F64 ? 8 : 4;
+    const size_t plane = (size_t)p.ny * L.pitch;
+    L.f_bytes = align_up(9 * plane * elem);
+    L.u_bytes = align_up(2 * plane * 8);
+    Geometry g{p.nx, p.ny, L.pitch, 0, 0};
+    L.part_bytes = align_up((size_t)diag_blocks(g) * 8 * sizeof(double));
+    L.out_bytes = align_up(8 * sizeof(double));
+    size_t o = 0;
+    L.off_f[0] = o; o += L.f_bytes;
+    L.off_f[1] = o; o += L.f_bytes;
+    L.off_u[0] = o; o += L.u_bytes;
+    L.off_u[1] = o; o += L.u_bytes;
+    L.off_part = o; o += L.part_bytes;
+    L.off_out = o; o += L.out_bytes;
+    L.total = o;
+    return L;
+}
+
+int check_params(const mclbm_params* p) {
+    if (!p) return fail(MCLBM_EINVAL, "params is NULL");
+    if (p->nx < 3 || p->ny < 3) return fail(MCLBM_EINVAL, "nx and ny must be >= 3 (got %d x %d)", p->nx, p->ny);
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31)
+        return fail(MCLBM_EINVAL, "lattice of %d x %d nodes exceeds 2^31 nodes", p->nx, p->ny);
+    if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
+        return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");
+    if (!(p->tau > 0.5)) return fail(MCLBM_EINVAL, "tau must exceed 0.5 (got %g)", p->tau);
+    if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(MCLBM_EINVAL, "nu must lie in (-1, 0.5) (got %g)", p->nu);
+    if (p->material < MCLBM_SVK || p->material > MCLBM_LINEAR)
+        return fail(MCLBM_EINVAL, "unknown material %d", p->material);
+    if (p->precision != MCLBM_F64 && p->precision != MCLBM_F32)
+        return fail(MCLBM_EINVAL, "unknown precision %d", p->precision);
+    if (!std::isfinite(p->body[0]) || !std::isfinite(p->body[1]))
+        return fail(MCLBM_EINVAL, "body force must be finite");
+    return MCLBM_OK;
+}
+
+// lattice speed c = sqrt(3) c_s, c_s = sqrt(mu/rho0) (Sect. 3.2); dt = dX / c
+double lattice_speed(const mclbm_params& p) { return std::sqrt(3.0 * p.mu / p.rho0); }
+
+int check_side(const mclbm_side_spec* s) {
+    if (!s) return fail(MCLBM_EINVAL, "side spec is NULL");
+    if (s->bc < MCLBM_DIRICHLET || s->bc > MCLBM_PERIODIC) return fail(MCLBM_EINVAL, "unknown wall type %d", s->bc);
+    if (s->kind < MCLBM_LOAD_ZERO || s->kind > MCLBM_LOAD_RICKER)
+        return fail(MCLBM_EINVAL, "unknown load program %d", s->kind);
+    if (s->kind == MCLBM_LOAD_DISP_RAMP && s->bc != MCLBM_DIRICHLET)
+        return fail(MCLBM_EINVAL, "DISP_RAMP prescribes a wall speed and needs a Dirichlet side");
+    const bool need_t1 = s->kind == MCLBM_LOAD_DISP_RAMP || s->kind == MCLBM_LOAD_LINEAR_RAMP ||
+                         s->kind == MCLBM_LOAD_SIN2_RAMP || s->kind == MCLBM_LOAD_SIN_PULSE;
+    if (need_t1 && !(s->t1 > 0)) return fail(MCLBM_EINVAL, "load program %d needs t1 > 0", s->kind);
+    if ((s->kind == MCLBM_LOAD_GAUSS || s->kind == MCLBM_LOAD_RICKER) && !(s->width > 0))
+        return fail(MCLBM_EINVAL, "load program %d needs width > 0", s->kind);
+    if (!std::isfinite(s->amp[0]) || !std::isfinite(s->amp[1])) return fail(MCLBM_EINVAL, "load amplitude must be finite");
+    return MCLBM_OK;
+}
+
+}  // namespace
+
+struct mclbm_sim {
+    mclbm_params p;
+    Layout L;
+    char* arena;
+    hipStream_t stream;
+    Geometry g;
+    Coef k;
+    double dt;
+    mclbm_side_spec side[4];
+    int cur;       // which of the two population / displacement buffers is current
+    int64_t n;     // steps since init
+    bool inited;
+};
+
+namespace {
+
+// Time program of a wall load at step n.
+double load_scale(const mclbm_side_spec& s, double n) {
+    switch (s.kind) {
+    case MCLBM_LOAD_ZERO: return 0.0;
+    case MCLBM_LOAD_CONST: return 1.0;
+    case MCLBM_LOAD_LINEAR_RAMP: return n < s.t1 ? n / s.t1 : 1.0;
+    case MCLBM_LOAD_SIN2_RAMP: {
+        if (n >= s.t1) return 1.0;
+        const double v = std::sin(M_PI * n / (2.0 * s.t1));
+        return v * v;
+    }
+    case MCLBM_LOAD_SIN_PULSE: return n < s.t1 ? std::sin(M_PI * n / s.t1) : 0.0;
+    case MCLBM_LOAD_GAUSS: {
+        if (n > s.t1) return 0.0;
+        const double d = n - s.t0;
+        return std::exp(-d * d / (2.0 * s.width * s.width));
+    }
+    case MCLBM_LOAD_RICKER: {
+        if (n >= s.t1) return 0.0;
+        const double d2 = (n - s.t0) * (n - s.t0);
+        return 2.0 / std::sqrt(3.0 * s.width * std::sqrt(M_PI)) * (1.0 - d2 / s.width) *
+               std::exp(-0.5 * d2 / s.width);
+    }
+    default: return 0.0;
+    }
+}
+
+Walls walls_at(const mclbm_sim* s, int64_t n) {
+    Walls w;
+    for (int i = 0; i < 4; i++) {
+        const mclbm_side_spec& sp = s->side[i];
+        w.bc[i] = sp.bc;
+        double k;
+        if (sp.kind == MCLBM_LOAD_DISP_RAMP)  // j* = rho0 * wall speed while the ramp runs
+            k = (double)n < sp.t1 ? s->p.rho0 / (sp.t1 * s->dt) : 0.0;
+        else
+            k = load_scale(sp, (double)n);
+        w.val[i][0] = sp.amp[0] * k;
+        w.val[i][1] = sp.amp[1] * k;
+    }
+    return w;
+}
+
+int check_pairs(const mclbm_sim* s) {
+    const bool l = s->side[MCLBM_LEFT].bc == MCLBM_PERIODIC, r = s->side[MCLBM_RIGHT].bc == MCLBM_PERIODIC;
+    const bool b = s->side[MCLBM_BOTTOM].bc == MCLBM_PERIODIC, t = s->side[MCLBM_TOP].bc == MCLBM_PERIODIC;
+    if (l != r) return fail(MCLBM_EINVAL, "periodic left/right sides must be set as a pair");
+    if (b != t) return fail(MCLBM_EINVAL, "periodic bottom/top sides must be set as a pair");
+    return MCLBM_OK;
+}
+
+void* at(const mclbm_sim* s, size_t off) { return s->arena + off; }
+
+InitLike base_args(const mclbm_sim* s, const double* u) {
+    InitLike b;
+    b.u = u;
+    b.g = s->g;
+    b.inv_dx = s->k.inv_dx;
+    b.inv_c2 = s->k.inv_c2;
+    b.sig_b[0] = s->k.sig_b[0];
+    b.sig_b[1] = s->k.sig_b[1];
+    b.lam = s->k.lam;
+    b.mu = s->k.mu;
+    b.rho0 = s->k.rho0;
+    return b;
+}
+
+// copy a compact [2][ny][nx] FP64 field into a pitched [2][ny][pitch] buffer
+int put_field2(mclbm_sim* s, double* dst, const double* src, int on_device) {
+    const size_t plane = (size_t)s->g.ny * s->g.pitch;
+    if (!src) {
+        HIP_TRY(hipMemsetAsync(dst, 0, 2 * plane * sizeof(double), s->stream));
+        return MCLBM_OK;
+    }
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIP_TRY(hipMemsetAsync(dst, 0, 2 * plane * sizeof(double), s->stream));
+    for (int c = 0; c < 2; c++)
+        HIP_TRY(hipMemcpy2DAsync(dst + c * plane, (size_t)s->g.pitch * sizeof(double),
+                                 src + (size_t)c * s->g.nx * s->g.ny, (size_t)s->g.nx * sizeof(double),
+                                 (size_t)s->g.nx * sizeof(double), (size_t)s->g.ny, kind, s->stream));
+    return MCLBM_OK;
+}
+
+}  // namespace
+
+MCLBM_EXPORT int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, double* dt_out) {
+    const int rc = check_params(p);
+    if (rc) return rc;
+    const Layout L = layout_of(*p);
+    if (arena_bytes) *arena_bytes = L.total;
+    if (dt_out) *dt_out = p->dx / lattice_speed(*p);
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_bytes, void* stream,
+                              mclbm_sim** out) {
+    const int rc = check_params(p);
+    if (rc) return rc;
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!arena) return fail(MCLBM_EINVAL, "arena is NULL");
+    if ((uintptr_t)arena % kAlign) return fail(MCLBM_ETOOSMALL, "arena must be %zu-byte aligned", kAlign);
+    const Layout L = layout_of(*p);
+    if (arena_bytes < L.total)
+        return fail(MCLBM_ETOOSMALL, "arena has %zu bytes, %zu needed", arena_bytes, L.total);
+    mclbm_sim* s = new (std::nothrow) mclbm_sim();
+    if (!s) return fail(MCLBM_EINVAL, "out of host memory");
+    s->p = *p;
+    s->L = L;
+    s->arena = static_cast<char*>(arena);
+    s->stream = static_cast<hipStream_t>(stream);
+    s->g = Geometry{p->nx, p->ny, L.pitch, 0, 0};
+    const double c = lattice_speed(*p);
+    s->dt = p->dx / c;
+    s->k.omega = 1.0 / p->tau;
+    s->k.c = c;
+    s->k.inv_c = 1.0 / c;
+    s->k.inv_c2 = 1.0 / (c * c);
+    s->k.inv_dx = 1.0 / p->dx;
+    s->k.ucoef = p->dx / (2.0 * p->rho0);
+    s->k.sig_b[0] = p->rho0 * p->body[0] * p->dx * s->k.inv_c2;
+    s->k.sig_b[1] = p->rho0 * p->body[1] * p->dx * s->k.inv_c2;
+    s->k.s_from_sig = c * c / p->dx;
+    s->k.lam = 2.0 * p->mu * p->nu / (1.0 - 2.0 * p->nu);  // plane strain
+    s->k.mu = p->mu;
+    s->k.rho0 = p->rho0;
+    for (int i = 0; i < 4; i++) {
+        std::memset(&s->side[i], 0, sizeof(mclbm_side_spec));
+        s->side[i].bc = MCLBM_NEUMANN;
+        s->side[i].kind = MCLBM_LOAD_ZERO;
+    }
+    s->cur = 0;
+    s->n = 0;
+    s->inited = false;
+    *out = s;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_set_side(mclbm_sim* s, int side, const mclbm_side_spec* spec) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (side < MCLBM_LEFT || side > MCLBM_TOP) return fail(MCLBM_EINVAL, "unknown side %d", side);
+    const int rc = check_side(spec);
+    if (rc) return rc;
+    if (s->inited && (spec->bc == MCLBM_PERIODIC) != (s->side[side].bc == MCLBM_PERIODIC))
+        return fail(MCLBM_ESTATE, "periodicity of a side can only change before mclbm_init");
+    s->side[side] = *spec;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, int on_device) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    int rc = check_pairs(s);
+    if (rc) return rc;
+    s->g.px = s->side[MCLBM_LEFT].bc == MCLBM_PERIODIC;
+    s->g.py = s->side[MCLBM_BOTTOM].bc == MCLBM_PERIODIC;
+    s->cur = 0;
+    double* u = static_cast<double*>(at(s, s->L.off_u[0]));
+    double* stage = static_cast<double*>(at(s, s->L.off_u[1]));
+    if ((rc = put_field2(s, u, u0, on_device))) return rc;
+    if ((rc = put_field2(s, stage, j0, on_device))) return rc;
+    InitArgs a;
+    a.b = base_args(s, u);
+    a.f = at(s, s->L.off_f[0]);
+    a.j0 = stage;
+    a.rho0 = s->p.rho0;
+    a.inv_c = s->k.inv_c;
+    HIP_TRY(launch_init(s->p.precision == MCLBM_F64, a, s->stream));
+    s->n = 0;
+    s->inited = true;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_step before mclbm_init");
+    if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+    const int f64 = s->p.precision == MCLBM_F64;
+    for (int64_t i = 0; i < nsteps; i++) {
+        StepArgs a;
+        a.fsrc = at(s, s->L.off_f[s->cur]);
+        a.fdst = at(s, s->L.off_f[1 - s->cur]);
+        a.usrc = static_cast<const double*>(at(s, s->L.off_u[s->cur]));
+        a.udst = static_cast<double*>(at(s, s->L.off_u[1 - s->cur]));
+        a.g = s->g;
+        a.k = s->k;
+        a.w = walls_at(s, s->n);
+        HIP_TRY(launch_step(f64, s->p.material, a, s->stream));
+        s->cur = 1 - s->cur;
+        s->n++;
+    }
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int64_t mclbm_stepno(const mclbm_sim* s) { return s ? s->n : -1; }
+
+MCLBM_EXPORT int mclbm_field_components(int field) {
+    switch (field) {
+    case MCLBM_FIELD_U: case MCLBM_FIELD_J: case MCLBM_FIELD_S: return 2;
+    case MCLBM_FIELD_R: return 1;
+    case MCLBM_FIELD_PI: return 3;
+    case MCLBM_FIELD_H: case MCLBM_FIELD_P: return 4;
+    default: return 0;
+    }
+}
+
+MCLBM_EXPORT int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_read before mclbm_init");
+    const int nc = mclbm_field_components(field);
+    if (!nc) return fail(MCLBM_EINVAL, "unknown field %d", field);
+    if (!dst) return fail(MCLBM_EINVAL, "dst is NULL");
+    ReadArgs a;
+    a.b = base_args(s, static_cast<const double*>(at(s, s->L.off_u[s->cur])));
+    a.f = at(s, s->L.off_f[s->cur]);
+    // a host destination is staged in the idle population buffer (>= 32 B per node)
+    a.dst = on_device ? dst : static_cast<double*>(at(s, s->L.off_f[1 - s->cur]));
+    a.field = field;
+    a.c = s->k.c;
+    a.s_from_sig = s->k.s_from_sig;
+    a.partial = nullptr;
+    HIP_TRY(launch_read(s->p.precision == MCLBM_F64, s->p.material, a, s->stream));
+    const size_t bytes = (size_t)nc * s->g.nx * s->g.ny * sizeof(double);
+    if (!on_device) HIP_TRY(hipMemcpyAsync(dst, a.dst, bytes, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_diag before mclbm_init");
+    ReadArgs a;
+    a.b = base_args(s, static_cast<const double*>(at(s, s->L.off_u[s->cur])));
+    a.f = at(s, s->L.off_f[s->cur]);
+    a.dst = nullptr;
+    a.field = 0;
+    a.c = s->k.c;
+    a.s_from_sig = s->k.s_from_sig;
+    a.partial = static_cast<double*>(at(s, s->L.off_part));
+    double* dout = static_cast<double*>(at(s, s->L.off_out));
+    HIP_TRY(launch_diag(s->p.precision == MCLBM_F64, s->p.material, a, dout, s->stream));
+    double h[5];
+    HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    out->step = s->n;
+    out->momentum[0] = h[0];
+    out->momentum[1] = h[1];
+    out->ekin = h[2];
+    out->max_u = std::sqrt(h[3]);
+    out->nonfinite = h[4] != 0.0;
+    if (out->nonfinite) return fail(MCLBM_EUNSTABLE, "non-finite u or j at step %lld", (long long)s->n);
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT size_t mclbm_state_bytes(const mclbm_sim* s) {
+    return s ? s->L.f_bytes + s->L.u_bytes + sizeof(int64_t) : 0;
+}
+
+MCLBM_EXPORT int mclbm_save(mclbm_sim* s, void* dst, int on_device) {
+    if (!s || !dst) return fail(MCLBM_EINVAL, "NULL argument");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_save before mclbm_init");
+    char* d = static_cast<char*>(dst);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIP_TRY(hipMemcpyAsync(d, at(s, s->L.off_f[s->cur]), s->L.f_bytes, kind, s->stream));
+    HIP_TRY(hipMemcpyAsync(d + s->L.f_bytes, at(s, s->L.off_u[s->cur]), s->L.u_bytes, kind, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    const int64_t n = s->n;
+    if (on_device) HIP_TRY(hipMemcpy(d + s->L.f_bytes + s->L.u_bytes, &n, sizeof n, hipMemcpyHostToDevice));
+    else std::memcpy(d + s->L.f_bytes + s->L.u_bytes, &n, sizeof n);
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_load(mclbm_sim* s, const void* src, int on_device) {
+    if (!s || !src) return fail(MCLBM_EINVAL, "NULL argument");
+    int rc = check_pairs(s);
+    if (rc) return rc;
+    s->g.px = s->side[MCLBM_LEFT].bc == MCLBM_PERIODIC;
+    s->g.py = s->side[MCLBM_BOTTOM].bc == MCLBM_PERIODIC;
+    const char* d = static_cast<const char*>(src);
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    s->cur = 0;
+    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_f[0]), d, s->L.f_bytes, kind, s->stream));
+    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_u[0]), d + s->L.f_bytes, s->L.u_bytes, kind, s->stream));
+    int64_t n = 0;
+    if (on_device) HIP_TRY(hipMemcpy(&n, d + s->L.f_bytes + s->L.u_bytes, sizeof n, hipMemcpyDeviceToHost));
+    else std::memcpy(&n, d + s->L.f_bytes + s->L.u_bytes, sizeof n);
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    s->n = n;
+    s->inited = true;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_destroy(mclbm_sim* s) {
+    delete s;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT const char* mclbm_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,152 @@
+// Device-side building blocks of the moment-chain LBM step (gfx950).
+//
+// Everything on the device works in lattice-scaled moments of the populations:
+//   r = sum f,  M1 = sum e f,  M2 = sum e e f
+// with e_q the integer D2Q9 directions (Tab. 1), so that the physical moments
+// are j = c M1 and Pi = c^2 M2 (c = dX/dt = sqrt(3) c_s, Sect. 3.2).  In these
+// variables the equilibrium of Sect. 3.2 is free of c:
+//   f_eq,q = w_q [ r + 3 e.M1 + (9 e.M2.e - 3 r |e|^2 - 3 tr M2 + 2 r) / 2 ]
+// the forcing term of Eq. forcing scaled by dt is dt psi_q = 3 w_q e.sigma with
+// sigma = dt S / c, the Dirichlet correction of Eq. bbcon is
+// -6 w_q e.(j*/c), and the Neumann rule of Eq. abbcon uses the same
+// expression as f_eq with M2 = Pi_bd / c^2 and no M1 term.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mclbm {
+
+// ---- kernel arguments ---------------------------------------------------------
+
+struct Geometry {
+    int nx, ny;   // nodes
+    int pitch;    // row pitch in elements (multiple of 64)
+    int px, py;   // periodic in x / y
+};
+
+struct Coef {
+    double omega;     // dt / tau, tau in units of dt
+    double c;         // lattice speed dX/dt
+    double inv_c;     // 1/c
+    double inv_c2;    // 1/c^2 = dt^2/dX^2 = rho0/(3 mu)
+    double inv_dx;    // 1/dX
+    double ucoef;     // dX / (2 rho0): trapezoidal rule in scaled moments
+    double sig_b[2];  // rho0 b dX / c^2: body-force part of sigma
+    double s_from_sig;// c / dt: S = sigma * c / dt
+    double lam, mu, rho0;
+};
+
+// Wall data of one step: type per side and its value at t_n (j* for
+// Dirichlet, T* for Neumann, physical units).
+struct Walls {
+    int bc[4];
+    double val[4][2];
+};
+
+enum { SIDE_L = 0, SIDE_R = 1, SIDE_B = 2, SIDE_T = 3 };
+enum { BC_DIR = 0, BC_NEU = 1, BC_PER = 2 };
+enum { MAT_SVK = 0, MAT_NH = 1, MAT_LIN = 2 };
+
+// ---- D2Q9, Tab. 1 ---------------------------------------------------------------
+
+__host__ __device__ constexpr int ex(int q) {
+    return (q == 1 || q == 5 || q == 8) ? 1 : ((q == 3 || q == 6 || q == 7) ? -1 : 0);
+}
+__host__ __device__ constexpr int ey(int q) {
+    return (q == 2 || q == 5 || q == 6) ? 1 : ((q == 4 || q == 7 || q == 8) ? -1 : 0);
+}
+__host__ __device__ constexpr int opp(int q) {
+    return q == 0 ? 0 : (q <= 4 ? ((q + 1) % 4) + 1 : ((q - 3) % 4) + 5);
+}
+template <typename T>
+__host__ __device__ constexpr T wq(int q) {
+    return q == 0 ? T(4) / T(9) : (q <= 4 ? T(1) / T(9) : T(1) / T(36));
+}
+
+// Equilibrium in scaled moments (see the file comment).
+template <typename T>
+__device__ __forceinline__ T feq_q(int q, T r, T m1x, T m1y, T m2xx, T m2xy, T m2yy) {
+    const T X = T(ex(q)), Y = T(ey(q));
+    const T eM1 = X * m1x + Y * m1y;
+    const T eM2e = X * X * m2xx + T(2) * X * Y * m2xy + Y * Y * m2yy;
+    const T e2 = X * X + Y * Y;
+    return wq<T>(q) * (r + T(3) * eM1 +
+                       T(0.5) * (T(9) * eM2e - T(3) * r * e2 - T(3) * (m2xx + m2yy) + T(2) * r));
+}
+
+// ---- materials, Sect. 4 (plane strain) ------------------------------------------------
+
+// First Piola-Kirchhoff stress P(H), H_ab = d u_a / d X_b, order (xx, xy, yx, yy).
+template <typename T, int MAT>
+__device__ __forceinline__ void first_pk(T hxx, T hxy, T hyx, T hyy, T lam, T mu, T P[4]) {
+    if constexpr (MAT == MAT_SVK) {
+        // S = lam tr(E) I + 2 mu E, E = (H + H^T + H^T H)/2, P = (I + H) S
+        const T Exx = hxx + T(0.5) * (hxx * hxx + hyx * hyx);
+        const T Eyy = hyy + T(0.5) * (hxy * hxy + hyy * hyy);
+        const T Exy = T(0.5) * (hxy + hyx + hxx * hxy + hyx * hyy);
+        const T trE = Exx + Eyy;
+        const T Sxx = lam * trE + T(2) * mu * Exx;
+        const T Syy = lam * trE + T(2) * mu * Eyy;
+        const T Sxy = T(2) * mu * Exy;
+        P[0] = (T(1) + hxx) * Sxx + hxy * Sxy;
+        P[1] = (T(1) + hxx) * Sxy + hxy * Syy;
+        P[2] = hyx * Sxx + (T(1) + hyy) * Sxy;
+        P[3] = hyx * Sxy + (T(1) + hyy) * Syy;
+    } else if constexpr (MAT == MAT_NH) {
+        // S = lam/2 (J^2 - 1) C^-1 + mu (I - C^-1), P = F S
+        //   = mu (F - F^-T) + lam/2 (J^2 - 1) F^-T,   F^-T = (I + K) / J,
+        // K = cof(H) = [[hyy, -hyx], [-hxy, hxx]], and with d = J - 1 = tr H + det H
+        //   F - F^-T = (d I + J H - K) / J,  J^2 - 1 = d (d + 2):
+        // every term is O(H), so small strains keep their relative precision.
+        const T d = (hxx + hyy) + (hxx * hyy - hxy * hyx);
+        const T J = T(1) + d;
+        const T iJ = T(1) / J;
+        const T a = T(0.5) * lam * d * (d + T(2));
+        P[0] = iJ * (mu * (d + J * hxx - hyy) + a * (T(1) + hyy));
+        P[1] = iJ * (mu * (J * hxy + hyx) - a * hyx);
+        P[2] = iJ * (mu * (J * hyx + hxy) - a * hxy);
+        P[3] = iJ * (mu * (d + J * hyy - hxx) + a * (T(1) + hxx));
+    } else {
+        // Hooke's law of the linear-elastic scheme
+        const T tr = hxx + hyy;
+        P[0] = lam * tr + mu * (hxx + hxx);
+        P[1] = mu * (hxy + hyx);
+        P[2] = mu * (hyx + hxy);
+        P[3] = lam * tr + mu * (hyy + hyy);
+    }
+}
+
+// T = P(H) + Pi(H) with the stress of the bare chain Pi(H) = -mu (H + H^T + tr H I)
+// (Sect. 3.1: the source carries the divergence of T).
+template <typename T, int MAT>
+__device__ __forceinline__ void excess_stress(T hxx, T hxy, T hyx, T hyy, T lam, T mu, T out[4]) {
+    if constexpr (MAT == MAT_LIN) {
+        // P_lin + Pi(H) = (lam - mu) tr H I: exactly zero at nu = 1/4
+        const T d = (lam - mu) * (hxx + hyy);
+        out[0] = d; out[1] = T(0); out[2] = T(0); out[3] = d;
+    } else {
+        T P[4];
+        first_pk<T, MAT>(hxx, hxy, hyx, hyy, lam, mu, P);
+        const T tr = hxx + hyy;
+        const T sh = mu * (hxy + hyx);
+        out[0] = P[0] - mu * (hxx + hxx + tr);
+        out[1] = P[1] - sh;
+        out[2] = P[2] - sh;
+        out[3] = P[3] - mu * (hyy + hyy + tr);
+    }
+}
+
+// ---- finite differences, Sect. 3.2 ----------------------------------------------------
+// Central differences in the interior, first-order one-sided differences with the
+// inward neighbour at the outermost node of a non-periodic axis.
+
+__device__ __forceinline__ bool at_low(int g, int per) { return !per && g == 0; }
+__device__ __forceinline__ bool at_high(int g, int n, int per) { return !per && g == n - 1; }
+
+__device__ __forceinline__ int wrap(int g, int n) {
+    int r = g % n;
+    return r < 0 ? r + n : r;
+}
+
+}  // namespace mclbm

@@ -1,0 +1,49 @@
+// Internal interface between the host API (mclbm_api.cpp) and the kernels
+// (mclbm_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include "mclbm_device.hpp"
+
+namespace mclbm {
+
+struct StepArgs {
+    const void* fsrc;  // fc'_n, [9][ny][pitch] of float or double
+    void* fdst;        // fc'_{n+1}
+    const double* usrc;  // u_n, [2][ny][pitch]
+    double* udst;        // u_{n+1}
+    Geometry g;
+    Coef k;
+    Walls w;
+};
+
+// What the per-node helpers need: the displacement field and the constants of
+// the stress and source evaluation.
+struct InitLike {
+    const double* u;   // [2][ny][pitch]
+    Geometry g;
+    double inv_dx, inv_c2, sig_b[2], lam, mu, rho0;
+};
+
+struct InitArgs {
+    InitLike b;
+    void* f;           // fc'_0 out
+    const double* j0;  // [2][ny][pitch]
+    double rho0, inv_c;
+};
+
+struct ReadArgs {
+    InitLike b;
+    const void* f;     // fc'_n
+    double* dst;       // [comp][ny][nx] FP64
+    int field;
+    double c, s_from_sig;
+    double* partial;   // diagnostics: 8 doubles per block
+};
+
+hipError_t launch_step(int f64, int material, const StepArgs& a, hipStream_t st);
+hipError_t launch_init(int f64, const InitArgs& a, hipStream_t st);
+hipError_t launch_read(int f64, int material, const ReadArgs& a, hipStream_t st);
+hipError_t launch_diag(int f64, int material, const ReadArgs& a, double* out, hipStream_t st);
+int diag_blocks(const Geometry& g);
+
+}  // namespace mclbm

@@ -1,0 +1,255 @@
+"""Python binding of the mclbm C ABI (include/mclbm.h).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libmclbm.so.  The functions below carry the names of the C entry points; the
+``Sim`` class wraps one simulation whose device arena is a torch tensor and
+whose work goes to torch's current HIP stream.  Importing this module fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmclbm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2502_00920_amd.build` "
+                      "(hipcc, gfx950); there is no fallback implementation")
+
+_lib = C.CDLL(LIB_PATH)
+
+# ---- enums (include/mclbm.h) ---------------------------------------------------------
+MCLBM_OK, MCLBM_EINVAL, MCLBM_ETOOSMALL, MCLBM_EHIP, MCLBM_EUNSTABLE, MCLBM_ESTATE = 0, -1, -2, -3, -4, -5
+MATERIAL = {"svk": 0, "neohooke": 1, "linear": 2}
+PRECISION = {"f64": 0, "f32": 1}
+SIDE = {"left": 0, "right": 1, "bottom": 2, "top": 3}
+BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
+LOAD = {"zero": 0, "const": 1, "disp_ramp": 2, "linear_ramp": 3, "sin2_ramp": 4,
+        "sin_pulse": 5, "gauss": 6, "ricker": 7}
+FIELD = {"u": 0, "j": 1, "r": 2, "pi": 3, "h": 4, "p": 5, "s": 6}
+
+
+class mclbm_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("material", C.c_int32),
+                ("precision", C.c_int32), ("dx", C.c_double), ("rho0", C.c_double),
+                ("mu", C.c_double), ("nu", C.c_double), ("tau", C.c_double),
+                ("body", C.c_double * 2)]
+
+
+class mclbm_side_spec(C.Structure):
+    _fields_ = [("bc", C.c_int32), ("kind", C.c_int32), ("amp", C.c_double * 2),
+                ("t0", C.c_double), ("t1", C.c_double), ("width", C.c_double)]
+
+
+class mclbm_diag_out(C.Structure):
+    _fields_ = [("step", C.c_int64), ("momentum", C.c_double * 2), ("ekin", C.c_double),
+                ("max_u", C.c_double), ("nonfinite", C.c_int32)]
+
+
+_vp, _i, _i64, _sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
+_sig = {
+    "mclbm_plan": (_i, [C.POINTER(mclbm_params), C.POINTER(_sz), C.POINTER(C.c_double)]),
+    "mclbm_create": (_i, [C.POINTER(mclbm_params), _vp, _sz, _vp, C.POINTER(_vp)]),
+    "mclbm_set_side": (_i, [_vp, _i, C.POINTER(mclbm_side_spec)]),
+    "mclbm_init": (_i, [_vp, _vp, _vp, _i]),
+    "mclbm_step": (_i, [_vp, _i64]),
+    "mclbm_stepno": (_i64, [_vp]),
+    "mclbm_field_components": (_i, [_i]),
+    "mclbm_read": (_i, [_vp, _i, _vp, _i]),
+    "mclbm_diag": (_i, [_vp, C.POINTER(mclbm_diag_out)]),
+    "mclbm_state_bytes": (_sz, [_vp]),
+    "mclbm_save": (_i, [_vp, _vp, _i]),
+    "mclbm_load": (_i, [_vp, _vp, _i]),
+    "mclbm_destroy": (_i, [_vp]),
+    "mclbm_last_error": (C.c_char_p, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class MclbmError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: status {code}: {mclbm_last_error()}")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != MCLBM_OK:
+        raise MclbmError(rc, where)
+
+
+# ---- the C entry points, same names ------------------------------------------------------
+
+def mclbm_last_error() -> str:
+    return _lib.mclbm_last_error().decode()
+
+
+def mclbm_plan(p: mclbm_params):
+    """(arena_bytes, dt) for these parameters."""
+    nbytes, dt = _sz(0), C.c_double(0)
+    _check(_lib.mclbm_plan(C.byref(p), C.byref(nbytes), C.byref(dt)), "mclbm_plan")
+    return nbytes.value, dt.value
+
+
+def mclbm_create(p: mclbm_params, arena_ptr: int, arena_bytes: int, stream_ptr: int) -> int:
+    h = _vp()
+    _check(_lib.mclbm_create(C.byref(p), _vp(arena_ptr), arena_bytes, _vp(stream_ptr), C.byref(h)),
+           "mclbm_create")
+    return h.value
+
+
+def mclbm_set_side(h: int, side: int, spec: mclbm_side_spec) -> None:
+    _check(_lib.mclbm_set_side(_vp(h), side, C.byref(spec)), "mclbm_set_side")
+
+
+def mclbm_init(h: int, u0_ptr: Optional[int], j0_ptr: Optional[int], on_device: int) -> None:
+    _check(_lib.mclbm_init(_vp(h), _vp(u0_ptr), _vp(j0_ptr), on_device), "mclbm_init")
+
+
+def mclbm_step(h: int, nsteps: int) -> None:
+    _check(_lib.mclbm_step(_vp(h), int(nsteps)), "mclbm_step")
+
+
+def mclbm_stepno(h: int) -> int:
+    return _lib.mclbm_stepno(_vp(h))
+
+
+def mclbm_field_components(field: int) -> int:
+    return _lib.mclbm_field_components(field)
+
+
+def mclbm_read(h: int, field: int, dst_ptr: int, on_device: int) -> None:
+    _check(_lib.mclbm_read(_vp(h), field, _vp(dst_ptr), on_device), "mclbm_read")
+
+
+def mclbm_diag(h: int) -> mclbm_diag_out:
+    out = mclbm_diag_out()
+    rc = _lib.mclbm_diag(_vp(h), C.byref(out))
+    if rc not in (MCLBM_OK, MCLBM_EUNSTABLE):
+        _check(rc, "mclbm_diag")
+    return out
+
+
+def mclbm_state_bytes(h: int) -> int:
+    return _lib.mclbm_state_bytes(_vp(h))
+
+
+def mclbm_save(h: int, dst_ptr: int, on_device: int) -> None:
+    _check(_lib.mclbm_save(_vp(h), _vp(dst_ptr), on_device), "mclbm_save")
+
+
+def mclbm_load(h: int, src_ptr: int, on_device: int) -> None:
+    _check(_lib.mclbm_load(_vp(h), _vp(src_ptr), on_device), "mclbm_load")
+
+
+def mclbm_destroy(h: int) -> None:
+    _lib.mclbm_destroy(_vp(h))
+
+
+# ---- convenience wrapper (torch owns the device memory and the stream) -------------------------
+
+def make_params(nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0, dx=1.0,
+                body=(0.0, 0.0)) -> mclbm_params:
+    p = mclbm_params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.material, p.precision = MATERIAL[material], PRECISION[precision]
+    p.dx, p.rho0, p.mu, p.nu, p.tau = float(dx), float(rho0), float(mu), float(nu), float(tau)
+    p.body[0], p.body[1] = float(body[0]), float(body[1])
+    return p
+
+
+def make_side(bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0) -> mclbm_side_spec:
+    s = mclbm_side_spec()
+    s.bc, s.kind = BC[bc], LOAD[kind]
+    s.amp[0], s.amp[1] = float(amp[0]), float(amp[1])
+    s.t0, s.t1, s.width = float(t0), float(t1), float(width)
+    return s
+
+
+class Sim:
+    """One simulation on a GPU.  Fields come back as float64 torch tensors
+    [comp, ny, nx] on the device (or numpy arrays with ``host=True``)."""
+
+    def __init__(self, nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0,
+                 dx=1.0, body=(0.0, 0.0), device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.nx, self.ny = int(nx), int(ny)
+        self.params = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material,
+                                  precision=precision, rho0=rho0, dx=dx, body=body)
+        self.arena_bytes, self.dt = mclbm_plan(self.params)
+        self.device = torch.device(device)
+        self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = mclbm_create(self.params, self.arena.data_ptr(), self.arena_bytes,
+                               self.stream.cuda_stream)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            mclbm_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    @property
+    def n(self) -> int:
+        return mclbm_stepno(self._h)
+
+    def set_side(self, side, bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0):
+        mclbm_set_side(self._h, SIDE[side], make_side(bc, kind, amp, t0, t1, width))
+
+    def init(self, u0=None, j0=None):
+        t = self.torch
+
+        def dev(a):
+            if a is None:
+                return None
+            return t.as_tensor(np.asarray(a, dtype=np.float64)).reshape(2, self.ny, self.nx) \
+                .to(self.device).contiguous()
+
+        u, j = dev(u0), dev(j0)
+        mclbm_init(self._h, None if u is None else u.data_ptr(), None if j is None else j.data_ptr(), 1)
+        self._keep = (u, j)  # alive until the copies on the stream have run
+        self.stream.synchronize()
+        self._keep = None
+
+    def step(self, n: int = 1):
+        mclbm_step(self._h, n)
+
+    def read(self, field: str, host: bool = True):
+        nc = mclbm_field_components(FIELD[field])
+        out = self.torch.empty((nc, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        mclbm_read(self._h, FIELD[field], out.data_ptr(), 1)
+        return out.cpu().numpy() if host else out
+
+    def diag(self) -> Dict:
+        d = mclbm_diag(self._h)
+        return {"step": d.step, "momentum": np.array([d.momentum[0], d.momentum[1]]),
+                "ekin": d.ekin, "max_u": d.max_u, "nonfinite": bool(d.nonfinite)}
+
+    def save(self):
+        buf = self.torch.empty(mclbm_state_bytes(self._h), dtype=self.torch.uint8, device=self.device)
+        mclbm_save(self._h, buf.data_ptr(), 1)
+        return buf
+
+    def load(self, buf):
+        mclbm_load(self._h, buf.data_ptr(), 1)
+
+
+def sim_from_workload(w, precision="f64", **kw) -> Sim:
+    """A Sim set up with the sides of a workloads.Workload (not yet initialised)."""
+    s = Sim(w.nx, w.ny, mu=w.mu, nu=w.nu, tau=w.tau, material=w.material, precision=precision,
+            rho0=w.rho0, dx=w.dx, **kw)
+    for side, sd in w.sides.items():
+        s.set_side(side, sd.bc, sd.kind, sd.amp, sd.t0, sd.t1, sd.width)
+    return s

@@ -1,0 +1,112 @@
+"""The C ABI library loads, exports every entry point include/mclbm.h declares,
+and rejects bad arguments on the host (no GPU, no kernel launches)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mclbm.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mclbm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2502_00920_amd import mclbm
+    return mclbm
+
+
+def test_header_declares_the_api():
+    names = declared()
+    for n in ["mclbm_plan", "mclbm_create", "mclbm_set_side", "mclbm_init", "mclbm_step",
+              "mclbm_read", "mclbm_diag", "mclbm_save", "mclbm_load", "mclbm_destroy",
+              "mclbm_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(M):
+    lib = C.CDLL(M.LIB_PATH)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_plan_validation(M):
+    nbytes, dt = M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0))
+    assert dt == pytest.approx(1.0 / (3 * 0.05) ** 0.5, rel=1e-15)
+    assert nbytes > 2 * 9 * 32 * 64 * 8
+    bad = [dict(nx=2), dict(ny=1), dict(tau=0.5), dict(nu=0.5), dict(nu=-1.0), dict(mu=0.0),
+           dict(rho0=-1.0), dict(dx=0.0)]
+    for b in bad:
+        kw = dict(nx=32, ny=32, mu=0.05, nu=0.3, tau=1.0)
+        kw.update(b)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_plan(M.make_params(nx, ny, **kw))
+        assert e.value.code == M.MCLBM_EINVAL
+    p = M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0)
+    p.material = 7
+    with pytest.raises(M.MclbmError):
+        M.mclbm_plan(p)
+    p = M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0)
+    p.precision = 9
+    with pytest.raises(M.MclbmError):
+        M.mclbm_plan(p)
+
+
+def test_arena_scales_with_precision(M):
+    b64, _ = M.mclbm_plan(M.make_params(1000, 700, mu=0.05, nu=0.3, tau=0.55, precision="f64"))
+    b32, _ = M.mclbm_plan(M.make_params(1000, 700, mu=0.05, nu=0.3, tau=0.55, precision="f32"))
+    pitch = 1024
+    # two population buffers and two FP64 displacement buffers
+    assert b64 >= 2 * 9 * 700 * pitch * 8 + 2 * 2 * 700 * pitch * 8
+    assert b32 >= 2 * 9 * 700 * pitch * 4 + 2 * 2 * 700 * pitch * 8
+    assert b32 < b64
+
+
+def test_host_side_errors_without_gpu(M):
+    """create only records pointers; misuse is caught before any HIP call."""
+    p = M.make_params(16, 16, mu=0.05, nu=0.3, tau=1.0)
+    nbytes, _ = M.mclbm_plan(p)
+    fake = 1 << 20  # never dereferenced on these paths
+    with pytest.raises(M.MclbmError) as e:
+        M.mclbm_create(p, fake, nbytes - 1, 0)
+    assert e.value.code == M.MCLBM_ETOOSMALL
+    with pytest.raises(M.MclbmError) as e:
+        M.mclbm_create(p, fake + 8, nbytes, 0)
+    assert e.value.code == M.MCLBM_ETOOSMALL
+    h = M.mclbm_create(p, fake, nbytes, 0)
+    try:
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_step(h, 1)
+        assert e.value.code == M.MCLBM_ESTATE
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_read(h, 0, fake, 1)
+        assert e.value.code == M.MCLBM_ESTATE
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 5, M.make_side("neumann"))
+        assert e.value.code == M.MCLBM_EINVAL
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 0, M.make_side("neumann", "disp_ramp", (1, 0), t1=10))
+        assert e.value.code == M.MCLBM_EINVAL
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 0, M.make_side("dirichlet", "sin2_ramp", (1, 0), t1=0))
+        assert e.value.code == M.MCLBM_EINVAL
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 1, M.make_side("neumann", "gauss", (1, 0), t1=10, width=0))
+        assert e.value.code == M.MCLBM_EINVAL
+        # a periodic side without its partner is refused at init, before any copy
+        M.mclbm_set_side(h, 0, M.make_side("periodic"))
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_init(h, None, None, 1)
+        assert e.value.code == M.MCLBM_EINVAL
+        assert "pair" in M.mclbm_last_error()
+        assert M.mclbm_field_components(3) == 3 and M.mclbm_field_components(99) == 0
+        assert M.mclbm_stepno(h) == 0
+    finally:
+        M.mclbm_destroy(h)

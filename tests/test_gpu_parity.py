@@ -1,0 +1,286 @@
+"""GPU (HIP, gfx950) against the FP64 CPU oracle, through the C ABI.
+
+Bars (relative L2 over all nodes and components):
+  FP64 storage: u, P, j, r, Pi, S <= 1e-12
+  FP32 storage (FP64 displacement): u and P <= 1e-5
+Lattices span several 64 x 16 tiles with ragged tails, every wall type and
+corner combination, time-dependent loads on every wall, and the benchmark
+workloads (shortened where the oracle would take minutes).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00920_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(8, os.cpu_count() or 1)
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2502_00920_amd import mclbm
+    return mclbm
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def pair(M, nx, ny, sides, *, material, mu=0.05, nu=0.3, tau=0.55, precision="f64", u0=None,
+         j0=None, rho0=1.0, dx=1.0, body=(0.0, 0.0)):
+    o = oracle.Oracle(nx, ny, mu=mu, nu=nu, tau=tau, material=material, rho0=rho0, dx=dx,
+                      body=body, threads=THREADS)
+    s = M.Sim(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=precision, rho0=rho0,
+              dx=dx, body=body)
+    for side, spec in sides.items():
+        args = (spec,) if isinstance(spec, str) else tuple(spec)
+        o.set_side(side, *args)
+        s.set_side(side, *args)
+    o.init(u0, j0)
+    s.init(u0, j0)
+    return o, s
+
+
+def compare(o, s, fields=("u", "p", "j", "r", "pi", "s")):
+    return {f: rel(s.read(f), o.read(f)) for f in fields}
+
+
+def print_case(tag):
+    print(f"\n[case] {tag}", flush=True)
+
+
+# wall programs: time-dependent momentum on Dirichlet sides, traction on Neumann sides
+def walls(code):
+    """code: four letters for left, right, bottom, top in {D, N, P}."""
+    prog = {
+        "left": (("dirichlet", "sin_pulse", (2e-4, -1e-4), 0, 40), ("neumann", "sin2_ramp", (-4e-3, 1e-3), 0, 30)),
+        "right": (("dirichlet", "const", (3e-4, 1e-4)), ("neumann", "sin2_ramp", (5e-3, -2e-3), 0, 25)),
+        "bottom": (("dirichlet", "linear_ramp", (-1e-4, 2e-4), 0, 30), ("neumann", "const", (1e-3, -3e-3))),
+        "top": (("dirichlet", "sin_pulse", (1e-4, 2e-4), 0, 35), ("neumann", "sin_pulse", (2e-3, 4e-3), 0, 45)),
+    }
+    out = {}
+    for side, c in zip(W.SIDES, code):
+        out[side] = "periodic" if c == "P" else prog[side][0 if c == "D" else 1]
+    return out
+
+
+CASES = [
+    # (nx, ny, wall code, material)
+    (150, 37, "DNDN", "svk"),
+    (150, 37, "NNNN", "neohooke"),
+    (67, 19, "DDDD", "neohooke"),
+    (67, 19, "DDNN", "svk"),
+    (129, 33, "NDND", "linear"),
+    (100, 20, "PPNN", "neohooke"),
+    (40, 70, "NNPP", "svk"),
+    (65, 17, "PPPP", "neohooke"),
+    (64, 16, "DNND", "svk"),
+    (70, 45, "PPDD", "linear"),
+]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny,code,material", CASES)
+def test_random_state_parity(M, nx, ny, code, material, precision):
+    print_case(f"random-state {nx}x{ny} {code} {material} {precision}")
+    u0 = W.smooth_field(nx, ny, 0.05, seed=nx + ny)
+    j0 = W.random_field(nx, ny, 1e-3, seed=nx * ny)
+    o, s = pair(M, nx, ny, walls(code), material=material, nu=0.2, precision=precision, u0=u0, j0=j0)
+    e0 = compare(o, s)
+    for n in (1, 9, 30):
+        o.step(n - o.n)
+        s.step(n - s.n)
+        e = compare(o, s)
+        print(n, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+        if precision == "f64":
+            for f, v in e.items():
+                assert v <= TOL["f64"], (n, f, v, e0)
+        else:
+            assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"], (n, e)
+
+
+@pytest.mark.parametrize("nx,ny", [(3, 3), (3, 40), (70, 3), (4, 5)])
+@pytest.mark.parametrize("code", ["DNDN", "NNNN", "PPPP", "DDPP"])
+def test_small_lattices(M, nx, ny, code):
+    print_case(f"small {nx}x{ny} {code}")
+    u0 = W.smooth_field(nx, ny, 0.02, seed=3)
+    o, s = pair(M, nx, ny, walls(code), material="neohooke", nu=0.2, u0=u0)
+    o.step(12)
+    s.step(12)
+    e = compare(o, s)
+    for f, v in e.items():
+        assert v <= TOL["f64"], (f, v)
+
+
+def test_body_force_and_units(M):
+    """rho0 != 1, dx != 1 and a body force b."""
+    print_case("body force / units")
+    nx, ny = 90, 41
+    u0 = W.smooth_field(nx, ny, 0.03, seed=9) * 0.5
+    o, s = pair(M, nx, ny, walls("DNNN"), material="svk", mu=0.7, nu=0.15, tau=0.6, rho0=2.5,
+                dx=0.5, body=(1e-3, -2e-3), u0=u0)
+    o.step(20)
+    s.step(20)
+    e = compare(o, s)
+    for f, v in e.items():
+        assert v <= TOL["f64"], (f, v)
+
+
+# ---- the benchmark workloads --------------------------------------------------------------
+
+def run_workload(M, w, precision, checkpoints):
+    o, s = pair(M, w.nx, w.ny, {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()},
+                material=w.material, mu=w.mu, nu=w.nu, tau=w.tau, precision=precision, u0=w.u0())
+    out = []
+    for n in checkpoints:
+        o.step(n - o.n)
+        s.step(n - s.n)
+        e = compare(o, s, ("u", "p", "j"))
+        out.append((n, e, o.diag()["max_u"]))
+        print(w.name, precision, n, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tension32(M, precision):
+    """32x32 SVK tension (tau = 1): parity over the first 1500 of its 3000 steps;
+    with nu = 0.3 beyond the 1/4 bound of first-order boundary stencils the run
+    later loses stability on both sides."""
+    print_case(f"tension32 {precision}")
+    for n, e, umax in run_workload(M, W.tension32(), precision, [100, 500, 1500]):
+        assert np.isfinite(umax)
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_shear128(M, precision):
+    print_case(f"shear128 nu=0.25 {precision}")
+    for n, e, umax in run_workload(M, W.shear128(0.25), precision, [200, 1000]):
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_beam2048(M, precision):
+    print_case(f"beam2048x128 {precision}")
+    for n, e, umax in run_workload(M, W.beam2048(), precision, [50, 150]):
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tension1024(M, precision):
+    print_case(f"tension1024 {precision}")
+    w = W.tension_large(1024, 1000)
+    for n, e, umax in run_workload(M, w, precision, [10, 30]):
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+# ---- properties at size ----------------------------------------------------------------------
+
+def test_rest_state_bitwise(M):
+    print_case("rest state 700x300")
+    s = M.Sim(700, 300, mu=0.05, nu=0.3, tau=0.55, material="neohooke")
+    for side, b in zip(W.SIDES, ["dirichlet", "neumann", "neumann", "dirichlet"]):
+        s.set_side(side, b)
+    s.init()
+    s.step(20)
+    for f in ("u", "j", "r", "pi", "p"):
+        assert np.all(s.read(f) == 0.0)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_homogeneous_tension_at_size(M, precision):
+    print_case(f"homogeneous tension 1000x600 {precision}")
+    mu, nu, l1 = 0.05, 0.2, 1.25
+    l2 = math.sqrt((1 - nu * l1 ** 2) / (1 - nu))
+    P11 = mu * l1 * (l1 ** 2 - 1) / (1 - nu)
+    nx, ny = 1000, 600
+    X = (np.arange(nx) + 0.5)[None, :].repeat(ny, 0)
+    Y = (np.arange(ny) + 0.5)[:, None].repeat(nx, 1)
+    u0 = np.stack([(l1 - 1) * X, (l2 - 1) * Y])
+    s = M.Sim(nx, ny, mu=mu, nu=nu, tau=0.55, material="svk", precision=precision)
+    s.set_side("left", "neumann", "const", (-P11, 0.0))
+    s.set_side("right", "neumann", "const", (P11, 0.0))
+    s.init(u0)
+    s.step(40)
+    tol = 1e-12 if precision == "f64" else 1e-6
+    assert rel(s.read("u"), u0) < tol
+    P = s.read("p")
+    assert np.abs(P[0] / P11 - 1).max() < (1e-9 if precision == "f64" else 1e-3)
+
+
+def test_rigid_translation_at_size(M):
+    print_case("rigid translation 513x257")
+    nx, ny = 513, 257
+    v0 = (0.003, -0.0017)
+    s = M.Sim(nx, ny, mu=0.05, nu=0.3, tau=0.55, material="svk")
+    j0 = np.zeros((2, ny, nx))
+    j0[0], j0[1] = v0
+    s.init(None, j0)
+    s.step(30)
+    u = s.read("u")
+    assert np.abs(u[0] - 30 * s.dt * v0[0]).max() < 1e-14
+    assert np.abs(u[1] - 30 * s.dt * v0[1]).max() < 1e-14
+
+
+# ---- determinism, checkpoints, diagnostics ------------------------------------------------------
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_bitwise_determinism_and_checkpoint(M, precision):
+    print_case(f"determinism + checkpoint {precision}")
+    w = W.shear128(0.25)
+    sides = {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()}
+    runs = []
+    for _ in range(2):
+        s = M.sim_from_workload(w, precision)
+        s.init(W.smooth_field(w.nx, w.ny, 0.02, seed=1))
+        s.step(300)
+        runs.append(s.read("u"))
+    assert np.array_equal(runs[0], runs[1])
+    s = M.sim_from_workload(w, precision)
+    s.init(W.smooth_field(w.nx, w.ny, 0.02, seed=1))
+    s.step(120)
+    buf = s.save()
+    s.step(180)
+    a = s.read("u")
+    t = M.sim_from_workload(w, precision)
+    t.load(buf)
+    assert t.n == 120
+    t.step(180)
+    assert np.array_equal(t.read("u"), a)
+    assert np.array_equal(a, runs[0])
+    del sides
+
+
+def test_diag_parity(M):
+    print_case("diagnostics")
+    nx, ny = 77, 45
+    o, s = pair(M, nx, ny, walls("DNNN"), material="svk", nu=0.2, u0=W.smooth_field(nx, ny, 0.04, 2),
+                j0=W.random_field(nx, ny, 1e-3, 3))
+    o.step(15)
+    s.step(15)
+    d, od = s.diag(), o.diag()
+    assert d["step"] == 15 and not d["nonfinite"]
+    np.testing.assert_allclose(d["momentum"], o.momentum(), rtol=1e-11, atol=1e-15)
+    assert d["ekin"] == pytest.approx(od["ekin"], rel=1e-11)
+    assert d["max_u"] == pytest.approx(od["max_u"], rel=1e-12)
+
+
+def test_diag_flags_nonfinite(M):
+    print_case("diagnostics flag a diverging run")
+    s = M.Sim(32, 32, mu=0.05, nu=0.45, tau=0.55, material="linear")
+    for side in W.SIDES:
+        s.set_side(side, "periodic")
+    s.init(W.random_field(32, 32, 1e-3, 1))
+    s.step(3000)
+    d = s.diag()
+    assert d["nonfinite"] or d["max_u"] > 1e3

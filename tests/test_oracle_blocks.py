@@ -222,3 +222,16 @@ def test_lattice_stress_cancels_hooke_at_quarter(seed):
     H = np.random.default_rng(seed).normal(size=(2, 2))
     T = oracle.stress_P("linear", lam, mu, H) + oracle.lattice_Pi(mu, H)
     assert np.all(T == 0.0)
+
+
+@pytest.mark.parametrize("material", ["svk", "neohooke"])
+@pytest.mark.parametrize("scale", [1e-4, 1e-7, 1e-10])
+def test_small_strain_keeps_relative_precision(material, scale):
+    """At |H| = scale the stress is Hooke's law to O(scale); a form that cancels
+    O(mu) terms to leave an O(mu |H|) result loses ~1e-16/scale instead."""
+    mu, nu = 0.05, 0.3
+    lam = lam_ps(mu, nu)
+    D = np.array([[0.3, -0.7], [1.1, 0.2]])
+    P = oracle.stress_P(material, lam, mu, scale * D) / scale
+    hooke = lam * np.trace(D) * np.eye(2) + mu * (D + D.T)
+    assert np.abs(P - hooke).max() <= 5 * scale * mu + 1e-14 * mu
