@@ -256,6 +256,243 @@ __global__ __launch_bounds__(NT) void step_kernel(StepArgs a) {
     }
 }
 
+// ---- step, y-marching form ------------------------------------------------------------------
+//
+// The same step without LDS or barriers.  Each wave owns a strip of MO = 58
+// columns (lanes 3..60, halo lanes 0..2 and 61..63) and marches down a chunk of
+// rows.  At iteration r it holds in registers the rows r..r+3 of u, r..r+2 of
+// T, r-1..r+1 of sigma and r-1..r+1 of the populations; x neighbours come from
+// lane shuffles, y neighbours from the rows it holds.  Every population and u
+// value of the strip is loaded once (the next rows one iteration ahead), plus
+// the halo columns and the rows that prime the pipeline of a chunk.
+
+constexpr int MH = 3, MO = 64 - 2 * MH;
+
+template <typename V>
+__device__ __forceinline__ V from_prev(V v) { return __shfl_up(v, 1); }    // value of lane l-1
+template <typename V>
+__device__ __forceinline__ V from_next(V v) { return __shfl_down(v, 1); }  // value of lane l+1
+
+template <typename T, int MAT>
+__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+    const Geometry g = a.g;
+    const int lane = threadIdx.x & 63;
+    const int item = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (item >= nstrip * nchunk) return;  // uniform per wave
+    const int strip = item % nstrip, chk = item / nstrip;
+    const int gxu = strip * MO - MH + lane;  // unwrapped column of this lane
+    int x = gxu;
+    bool xin;
+    if (g.px) { x = wrap(gxu, g.nx); xin = true; }
+    else xin = gxu >= 0 && gxu < g.nx;
+    const bool own = lane >= MH && lane < MH + MO && gxu < g.nx;
+    const bool pop = xin && lane >= MH - 1 && lane <= MH + MO;  // lanes whose populations are pulled
+    const bool atL = xin && at_low(x, g.px), atR = xin && at_high(x, g.nx, g.px);
+    const int yc = chk * chunk, ye = min(yc + chunk, g.ny);
+    const size_t plane = (size_t)g.ny * g.pitch;
+    const T* __restrict__ fs = reinterpret_cast<const T*>(a.fsrc);
+    T* __restrict__ fd = reinterpret_cast<T*>(a.fdst);
+    const double* __restrict__ u = a.usrc;
+    const double idx = a.k.inv_dx;
+    const T ic2 = T(a.k.inv_c2), sbx = T(a.k.sig_b[0]), sby = T(a.k.sig_b[1]);
+    const T lam = T(a.k.lam), mu = T(a.k.mu);
+
+    auto row_of = [&](int r, int& rr) -> bool {
+        if (g.py) { rr = wrap(r, g.ny); return true; }
+        rr = r;
+        return r >= 0 && r < g.ny;
+    };
+    auto load_u = [&](int r, double v[2]) {
+        int rr;
+        v[0] = 0.0; v[1] = 0.0;
+        if (xin && row_of(r, rr)) {
+            const size_t o = (size_t)rr * g.pitch + x;
+            v[0] = u[o];
+            v[1] = u[plane + o];
+        }
+    };
+    auto load_f = [&](int r, T f[9]) {
+        int rr;
+        if (pop && row_of(r, rr)) {
+            const size_t o = (size_t)rr * g.pitch + x;
+#pragma unroll
+            for (int q = 0; q < 9; q++) f[q] = fs[q * plane + o];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 9; q++) f[q] = T(0);
+        }
+    };
+    // T = P(H) + Pi(H) at row r from u at rows r-1, r, r+1 of this lane
+    auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4]) {
+        const double lx = from_prev(u0[0]), rx = from_next(u0[0]);
+        const double ly = from_prev(u0[1]), ry = from_next(u0[1]);
+        t[0] = t[1] = t[2] = t[3] = T(0);
+        int rr;
+        if (!(xin && row_of(r, rr))) return;
+        double ax = lx, bx = rx, ay = ly, by = ry, fx = 0.5 * idx;
+        if (atL) { ax = u0[0]; ay = u0[1]; fx = idx; }
+        else if (atR) { bx = u0[0]; by = u0[1]; fx = idx; }
+        double cx = um[0], dx = up[0], cy = um[1], dy = up[1], fy = 0.5 * idx;
+        if (!g.py && rr == 0) { cx = u0[0]; cy = u0[1]; fy = idx; }
+        else if (!g.py && rr == g.ny - 1) { dx = u0[0]; dy = u0[1]; fy = idx; }
+        excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx), T((dy - cy) * fy),
+                              lam, mu, t);
+    };
+    // sigma = dt S / c at row r from T at rows r-1, r, r+1 of this lane
+    auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2]) {
+        const T lxx = from_prev(t0[0]), rxx = from_next(t0[0]);
+        const T lyx = from_prev(t0[2]), ryx = from_next(t0[2]);
+        sg[0] = sg[1] = T(0);
+        int rr;
+        if (!(xin && row_of(r, rr))) return;
+        T axx = lxx, bxx = rxx, ayx = lyx, byx = ryx, fx = T(0.5);
+        if (atL) { axx = t0[0]; ayx = t0[2]; fx = T(1); }
+        else if (atR) { bxx = t0[0]; byx = t0[2]; fx = T(1); }
+        T cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3], fy = T(0.5);
+        if (!g.py && rr == 0) { cxy = t0[1]; cyy = t0[3]; fy = T(1); }
+        else if (!g.py && rr == g.ny - 1) { dxy = t0[1]; dyy = t0[3]; fy = T(1); }
+        sg[0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
+        sg[1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
+    };
+
+    // prime the pipeline for the first iteration r = yc - 2
+    double U0[2], U1[2], U2[2], U3[2], Un[2], tmp[2];
+    T T0[4], T1[4], T2[4];
+    T Gm[2] = {T(0), T(0)}, G0[2] = {T(0), T(0)}, G1[2];
+    T Fm[9], F0[9], F1[9], Fn[9];
+    load_u(yc - 3, tmp);
+    load_u(yc - 2, U0);
+    load_u(yc - 1, U1);
+    load_u(yc, U2);
+    load_u(yc + 1, Un);
+    load_f(yc - 1, Fn);
+    stress(yc - 2, tmp, U0, U1, T0);
+    stress(yc - 1, U0, U1, U2, T1);
+#pragma unroll
+    for (int q = 0; q < 9; q++) { Fm[q] = T(0); F0[q] = T(0); }
+
+    for (int r = yc - 2; r < ye; r++) {
+        U3[0] = Un[0]; U3[1] = Un[1];
+#pragma unroll
+        for (int q = 0; q < 9; q++) F1[q] = Fn[q];
+        if (r + 1 < ye) {  // next rows, one iteration ahead
+            load_u(r + 4, Un);
+            load_f(r + 2, Fn);
+        }
+        stress(r + 2, U1, U2, U3, T2);
+        sigma(r + 1, T0, T1, T2, G1);
+
+        if (r >= yc) {
+            // pull f(t_{r+1}) at row r: the forcing dt psi is added at the source node
+            T h[9];
+            h[0] = F0[0];
+            h[1] = F0[1] + T(3) * wq<T>(1) * G0[0];
+            h[3] = F0[3] - T(3) * wq<T>(3) * G0[0];
+            h[2] = Fm[2] + T(3) * wq<T>(2) * Gm[1];
+            h[5] = Fm[5] + T(3) * wq<T>(5) * (Gm[0] + Gm[1]);
+            h[6] = Fm[6] + T(3) * wq<T>(6) * (Gm[1] - Gm[0]);
+            h[4] = F1[4] - T(3) * wq<T>(4) * G1[1];
+            h[7] = F1[7] - T(3) * wq<T>(7) * (G1[0] + G1[1]);
+            h[8] = F1[8] + T(3) * wq<T>(8) * (G1[0] - G1[1]);
+            T f[9];
+            f[0] = h[0];
+            f[1] = from_prev(h[1]);
+            f[3] = from_next(h[3]);
+            f[2] = h[2];
+            f[5] = from_prev(h[5]);
+            f[6] = from_next(h[6]);
+            f[4] = h[4];
+            f[7] = from_next(h[7]);
+            f[8] = from_prev(h[8]);
+
+            const bool onB = at_low(r, g.py), onT = at_high(r, g.ny, g.py);
+            if (own && (atL || atR || onB || onT)) {
+                double rr0 = 0, mxx = 0, myy = 0;
+#pragma unroll
+                for (int q = 0; q < 9; q++) {
+                    rr0 += (double)F0[q];
+                    mxx += (double)(ex(q) * ex(q)) * (double)F0[q];
+                    myy += (double)(ey(q) * ey(q)) * (double)F0[q];
+                }
+                const double Txx = T0[0], Txy = T0[1], Tyx = T0[2], Tyy = T0[3];
+                const int wx = atL ? SIDE_L : SIDE_R, wy = onB ? SIDE_B : SIDE_T;
+                const double sxw = atL ? -1.0 : 1.0, syw = onB ? -1.0 : 1.0;
+                const double c2i = a.k.inv_c2;
+                const double Xxx = (-sxw * a.w.val[wx][0] + Txx) * c2i;
+                const double Xxy = (-sxw * a.w.val[wx][1] + Tyx) * c2i;
+                const double Yyy = (-syw * a.w.val[wy][1] + Tyy) * c2i;
+                const double Yxy = (-syw * a.w.val[wy][0] + Txy) * c2i;
+#pragma unroll
+                for (int p = 1; p < 9; p++) {
+                    const bool crx = (ex(p) > 0 && atL) || (ex(p) < 0 && atR);
+                    const bool cry = (ey(p) > 0 && onB) || (ey(p) < 0 && onT);
+                    if (!crx && !cry) continue;
+                    const int q = opp(p);  // the outgoing link the wall reflects
+                    const double fcq = (double)F0[q] + 3.0 * wq<double>(q) *
+                                       ((double)ex(q) * (double)G0[0] + (double)ey(q) * (double)G0[1]);
+                    double jx = 0.0, jy = 0.0;
+                    int nd = 0;
+                    if (crx && a.w.bc[wx] == BC_DIR) { jx += a.w.val[wx][0]; jy += a.w.val[wx][1]; nd++; }
+                    if (cry && a.w.bc[wy] == BC_DIR) { jx += a.w.val[wy][0]; jy += a.w.val[wy][1]; nd++; }
+                    double v;
+                    if (nd > 0) {
+                        // modified bounce-back, Eq. bbcon
+                        const double sc = a.k.inv_c / (double)nd;
+                        v = fcq - 6.0 * wq<double>(q) * ((double)ex(q) * jx + (double)ey(q) * jy) * sc;
+                    } else {
+                        // modified anti-bounce-back, Eq. abbcon
+                        double Mxx, Mxy, Myy;
+                        if (crx && cry) { Mxx = Xxx; Myy = Yyy; Mxy = 0.5 * (Xxy + Yxy); }
+                        else if (crx) { Mxx = Xxx; Mxy = Xxy; Myy = myy; }
+                        else { Mxx = mxx; Mxy = Yxy; Myy = Yyy; }
+                        const double X = ex(q), Y = ey(q);
+                        const double eMe = X * X * Mxx + 2.0 * X * Y * Mxy + Y * Y * Myy;
+                        const double e2 = X * X + Y * Y;
+                        v = -fcq + 2.0 * wq<double>(q) *
+                                       (rr0 + 0.5 * (9.0 * eMe - 3.0 * rr0 * e2 - 3.0 * (Mxx + Myy) + 2.0 * rr0));
+                    }
+                    f[p] = T(v);
+                }
+            }
+
+            T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
+            T o1x = T(0), o1y = T(0);
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                rho += f[q];
+                if (ex(q)) m1x += T(ex(q)) * f[q];
+                if (ey(q)) m1y += T(ey(q)) * f[q];
+                if (ex(q)) m2xx += f[q];
+                if (ex(q) * ey(q)) m2xy += T(ex(q) * ey(q)) * f[q];
+                if (ey(q)) m2yy += f[q];
+                if (ex(q)) o1x += T(ex(q)) * F0[q];
+                if (ey(q)) o1y += T(ey(q)) * F0[q];
+            }
+            if (own) {
+                const size_t o = (size_t)r * g.pitch + x;
+                a.udst[o] = U0[0] + a.k.ucoef * (double)(m1x + o1x + G0[0]);
+                a.udst[plane + o] = U0[1] + a.k.ucoef * (double)(m1y + o1y + G0[1]);
+                const T om = T(a.k.omega);
+#pragma unroll
+                for (int q = 0; q < 9; q++) {
+                    const T e = feq_q<T>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
+                    fd[q * plane + o] = f[q] + om * (e - f[q]);
+                }
+            }
+        }
+        // rotate the rows
+        U0[0] = U1[0]; U0[1] = U1[1];
+        U1[0] = U2[0]; U1[1] = U2[1];
+        U2[0] = U3[0]; U2[1] = U3[1];
+#pragma unroll
+        for (int c = 0; c < 4; c++) { T0[c] = T1[c]; T1[c] = T2[c]; }
+        Gm[0] = G0[0]; Gm[1] = G0[1];
+        G0[0] = G1[0]; G0[1] = G1[1];
+#pragma unroll
+        for (int q = 0; q < 9; q++) { Fm[q] = F0[q]; F0[q] = F1[q]; }
+    }
+}
+
 // ---- per-node helpers for init, read-out and diagnostics (FP64, global loads) ----------
 
 __device__ __forceinline__ double ld_u(const InitLike& a, int c, int gx, int gy) {
@@ -469,14 +706,25 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int n
 
 // ---- launchers ---------------------------------------------------------------------------------
 
+// rows per chunk of the marching kernel: enough waves to fill the chip twice
+// over, without letting the rows that prime each chunk dominate
+static int march_chunk(const Geometry& g, int nstrip) {
+    const long target = 16384;
+    long c = ((long)g.ny * nstrip + target - 1) / target;
+    c = c < 8 ? 8 : (c > 128 ? 128 : c);
+    return (int)c;
+}
+
 template <typename T>
 static hipError_t step_t(int material, const StepArgs& a, hipStream_t st) {
-    const int ntx = (a.g.nx + TX - 1) / TX, nty = (a.g.ny + TY - 1) / TY;
-    const dim3 grid(ntx * nty), block(NT);
+    const int nstrip = (a.g.nx + MO - 1) / MO;
+    const int chunk = march_chunk(a.g, nstrip);
+    const int nchunk = (a.g.ny + chunk - 1) / chunk;
+    const dim3 grid((nstrip * nchunk + 3) / 4), block(256);
     switch (material) {
-    case MAT_SVK: hipLaunchKernelGGL((step_kernel<T, MAT_SVK>), grid, block, 0, st, a); break;
-    case MAT_NH: hipLaunchKernelGGL((step_kernel<T, MAT_NH>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((step_kernel<T, MAT_LIN>), grid, block, 0, st, a); break;
+    case MAT_SVK: hipLaunchKernelGGL((march_kernel<T, MAT_SVK>), grid, block, 0, st, a, nstrip, nchunk, chunk); break;
+    case MAT_NH: hipLaunchKernelGGL((march_kernel<T, MAT_NH>), grid, block, 0, st, a, nstrip, nchunk, chunk); break;
+    default: hipLaunchKernelGGL((march_kernel<T, MAT_LIN>), grid, block, 0, st, a, nstrip, nchunk, chunk); break;
     }
     return hipGetLastError();
 }
