@@ -52,10 +52,10 @@ Layout layout_of(const mclbm_params& p) {
     Layout L;
     L.pitch = (p.nx + 63) / 64 * 64;
     const size_t elem = p.precision == MCLBM_F64 ? 8 : 4;
-    const size_t plane = (size_t)p.ny * L.pitch;
+    const size_t plane = (size_t)(p.ny + 1) * L.pitch;  // row ny takes halo-lane stores
     L.f_bytes = align_up(9 * plane * elem);
     L.u_bytes = align_up(2 * plane * 8);
-    Geometry g{p.nx, p.ny, L.pitch, 0, 0};
+    Geometry g{p.nx, p.ny, L.pitch, 0, 0, (long long)plane};
     L.part_bytes = align_up((size_t)diag_blocks(g) * 8 * sizeof(double));
     L.out_bytes = align_up(8 * sizeof(double));
     size_t o = 0;
@@ -72,8 +72,14 @@ Layout layout_of(const mclbm_params& p) {
 int check_params(const mclbm_params* p) {
     if (!p) return fail(MCLBM_EINVAL, "params is NULL");
     if (p->nx < 3 || p->ny < 3) return fail(MCLBM_EINVAL, "nx and ny must be >= 3 (got %d x %d)", p->nx, p->ny);
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31)
-        return fail(MCLBM_EINVAL, "lattice of %d x %d nodes exceeds 2^31 nodes", p->nx, p->ny);
+    // the device addresses three component planes through one 32-bit buffer range
+    {
+        const int64_t plane = (int64_t)(p->ny + 1) * ((p->nx + 63) / 64 * 64);
+        const int64_t elem = p->precision == MCLBM_F64 ? 8 : 4;
+        if (plane * 3 * elem >= ((int64_t)1 << 32) || plane * 2 * 8 >= ((int64_t)1 << 32))
+            return fail(MCLBM_EINVAL, "lattice of %d x %d nodes too large for one device buffer range "
+                        "(three planes must stay below 4 GiB)", p->nx, p->ny);
+    }
     if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
         return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");
     if (!(p->tau > 0.5)) return fail(MCLBM_EINVAL, "tau must exceed 0.5 (got %g)", p->tau);
@@ -193,7 +199,7 @@ InitLike base_args(const mclbm_sim* s, const double* u) {
 
 // copy a compact [2][ny][nx] FP64 field into a pitched [2][ny][pitch] buffer
 int put_field2(mclbm_sim* s, double* dst, const double* src, int on_device) {
-    const size_t plane = (size_t)s->g.ny * s->g.pitch;
+    const size_t plane = (size_t)s->g.plane;
     if (!src) {
         HIP_TRY(hipMemsetAsync(dst, 0, 2 * plane * sizeof(double), s->stream));
         return MCLBM_OK;
@@ -235,7 +241,7 @@ MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_b
     s->L = L;
     s->arena = static_cast<char*>(arena);
     s->stream = static_cast<hipStream_t>(stream);
-    s->g = Geometry{p->nx, p->ny, L.pitch, 0, 0};
+    s->g = Geometry{p->nx, p->ny, L.pitch, 0, 0, (long long)(p->ny + 1) * L.pitch};
     const double c = lattice_speed(*p);
     s->dt = p->dx / c;
     s->k.omega = 1.0 / p->tau;

@@ -20,9 +20,11 @@ namespace mclbm {
 // ---- kernel arguments ---------------------------------------------------------
 
 struct Geometry {
-    int nx, ny;   // nodes
-    int pitch;    // row pitch in elements (multiple of 64)
-    int px, py;   // periodic in x / y
+    int nx, ny;        // nodes
+    int pitch;         // row pitch in elements (multiple of 64)
+    int px, py;        // periodic in x / y
+    long long plane;   // elements per component plane: (ny + 1) rows; row ny takes
+                       // the stores of halo lanes and is never read
 };
 
 struct Coef {
