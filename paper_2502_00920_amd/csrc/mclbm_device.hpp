@@ -24,7 +24,7 @@ struct Geometry {
     int pitch;         // row pitch in elements (multiple of 64)
     int px, py;        // periodic in x / y
     long long plane;   // elements per component plane: (ny + 1) rows; row ny takes
-                       // the stores of halo lanes and is never read
+                       // the stores of the rows that prime a chunk and is never read
 };
 
 struct Coef {

@@ -16,8 +16,9 @@
 //   4. u_{n+1} = u_n + dt/(2 rho0) (j(t_{n+1}) + j(t_n)), both j carrying S_n
 //   5. fc'_{n+1} = (1 - omega) f + omega f_eq(r, M1, M2)
 // A step is two launches: march_kernel updates every node as an interior node
-// (one pass over HBM), then wall_kernel recomputes the nodes on non-periodic
-// walls (0.05 % of an 8192^2 lattice) with the wall rules.
+// (one pass over HBM, each wave owning 64 aligned columns of a band of rows),
+// then wall_kernel recomputes the nodes on non-periodic walls (0.05 % of an
+// 8192^2 lattice) with the wall rules.
 // HBM traffic per node and step: 9 populations read and written, u read and
 // written (FP64): 176 B in FP64, 104 B in FP32 storage.
 #include "mclbm_internal.hpp"
@@ -58,55 +59,71 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t ob, ui
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, ob, so, 0);
 }
 
-// ---- step: interior nodes, y-marching ------------------------------------------------------
-//
-// Each wave owns a strip of MO = 58 columns (lanes 3..60, halo lanes 0..2 and
-// 61..63) and marches down a chunk of rows.  At iteration r it holds in
-// registers the rows r..r+3 of u, r..r+2 of T, r-1..r+1 of sigma and r-1..r+1
-// of the populations; x neighbours come from lane shuffles, y neighbours from
-// the rows it holds.  No LDS, no barriers, no branches on wall nodes (whose
-// results wall_kernel overwrites).  Every population and u value of the strip
-// is loaded once (the next rows one iteration ahead), plus the halo columns and
-// the rows that prime the pipeline of a chunk.
-
-constexpr int MH = 3, MO = 64 - 2 * MH;
-
 template <typename V>
 __device__ __forceinline__ V from_prev(V v) { return __shfl_up(v, 1); }    // value of lane l-1
 template <typename V>
 __device__ __forceinline__ V from_next(V v) { return __shfl_down(v, 1); }  // value of lane l+1
 
+// ---- step: interior nodes, y-marching ------------------------------------------------------
+//
+// Each wave owns the 64 columns [64 s, 64 s + 64) of a strip, so that every
+// store covers whole cache lines (a partly written line costs a read-modify-
+// write in HBM).  The values lanes 0 and 63 need from the neighbouring columns
+// (u of x0-1 and x0+64, their T, and the pulled populations with their forcing)
+// come from a halo pass every HR rows: it gathers u on five columns per side,
+// computes T on three and sigma and the six pull sources on the neighbour
+// column, and leaves them in wave-private LDS (no barrier: only this wave reads
+// them).  The gathers of a halo pass are issued one block ahead.  Lanes beyond
+// nx compute on clamped (or, periodic, wrapped) data and store into the row
+// padding; rows that prime the pipeline store into row ny.
+
+constexpr int HR = 6;       // iterations per halo block
+constexpr int HK = HR + 6;  // halo rows per block: k = 0..HK-1 is row r0 - 3 + k
+
+template <typename T>
+struct Halo {
+    double u[2][HK][5][2];  // [side][k][column c][comp]; side 0: x0-3+c, side 1: x0+62+c
+    T t[2][HK][3][4];       // T at c = 1, 2, 3
+    T s[2][HK][2];          // sigma at c = 2
+    T h[2][HK][3];          // pull sources at c = 2: side 0 p = 1, 5, 8; side 1 p = 3, 6, 7
+};
+
+// orders this wave's LDS writes before its later reads by other lanes (the
+// LDS serves one wave's operations in issue order; this keeps the compiler's
+// order too)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int halo_pop(int side, int i) {
+    return side == 0 ? (i == 0 ? 1 : (i == 1 ? 5 : 8)) : (i == 0 ? 3 : (i == 1 ? 6 : 7));
+}
+
 template <typename T, int MAT>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+    __shared__ Halo<T> halo_lds[4];
     const Geometry g = a.g;
     const int lane = threadIdx.x & 63;
-    // the work item is uniform across the wave: keep it (and all row arithmetic) scalar
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6));
+    const int wv = threadIdx.x >> 6;
+    Halo<T>& hl = halo_lds[wv];
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
     if (item >= nstrip * nchunk) return;
     const int strip = item % nstrip, chk = item / nstrip;
-    const int gxu = strip * MO - MH + lane;  // unwrapped column of this lane
-    // The loop below is straight-line: every lane issues every load and store.
-    // Loads outside the lattice read a clamped address; their values only reach
-    // links into wall nodes, which wall_kernel recomputes, and the one-sided
-    // differences at the lattice edge never read them.  Stores of halo lanes and
-    // of the rows that prime the pipeline go to row ny of each plane, which
-    // nothing reads.  With no skipped memory operation the loads of the next rows
-    // stay in flight across an iteration and the stores are never waited for.
-    const bool xin = g.px ? true : (gxu >= 0 && gxu < g.nx);
-    const int x = g.px ? wrap(gxu, g.nx) : min(max(gxu, 0), g.nx - 1);
-    // population loads of lanes 0, 1, 62, 63 are never used: give them the
-    // address of lane 2 / 61, which the memory pipeline merges
-    const int lp = min(max(lane, MH - 1), MH + MO);
-    const int gxp = strip * MO - MH + lp;
-    const int xp = g.px ? wrap(gxp, g.nx) : min(max(gxp, 0), g.nx - 1);
-    const bool own = lane >= MH && lane < MH + MO && gxu < g.nx;
+    const int x0 = strip * 64;
+    const int vx = x0 + lane;  // this lane's column (< pitch)
+    // column -> column to address: periodic wrap, else clamped into the lattice
+    auto colp = [&](int c) -> int { return g.px ? wrap(c, g.nx) : min(max(c, 0), g.nx - 1); };
+    const int x = colp(vx);
+    const bool xin = g.px ? true : vx < g.nx;
     const bool atL = xin && at_low(x, g.px), atR = xin && at_high(x, g.nx, g.px);
     const int yc = chk * chunk, ye = min(yc + chunk, g.ny);
+    const int nblk = (ye - (yc - 2) + HR - 1) / HR;
     const size_t plane = (size_t)g.plane;
     const uint32_t pbT = (uint32_t)(plane * sizeof(T)), pbD = (uint32_t)(plane * sizeof(double));
     const T* fs = reinterpret_cast<const T*>(a.fsrc);
     T* fd = reinterpret_cast<T*>(a.fdst);
-    // resources: populations q in [3k, 3k + 3) at SGPR offset (q - 3k) planes
     const __amdgpu_buffer_rsrc_t rs0 = rsrc(fs, 3 * pbT), rs1 = rsrc(fs + 3 * plane, 3 * pbT),
                                  rs2 = rsrc(fs + 6 * plane, 3 * pbT);
     const __amdgpu_buffer_rsrc_t rd0 = rsrc(fd, 3 * pbT), rd1 = rsrc(fd + 3 * plane, 3 * pbT),
@@ -115,82 +132,158 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
     const double idx = a.k.inv_dx;
     const T ic2 = T(a.k.inv_c2), sbx = T(a.k.sig_b[0]), sby = T(a.k.sig_b[1]);
     const T lam = T(a.k.lam), mu = T(a.k.mu);
-    const uint32_t trash = (uint32_t)(g.ny * g.pitch + lane);  // row ny: written, never read
+    const uint32_t trash = (uint32_t)(g.ny * g.pitch + vx);  // row ny: written, never read
 
-    // row r (uniform) -> row to address, and whether it lies in the lattice
-    auto rowc = [&](int r, bool& ok) -> int {
-        if (g.py) { ok = true; return wrap(r, g.ny); }
-        ok = r >= 0 && r < g.ny;
-        return min(max(r, 0), g.ny - 1);
-    };
+    // row r -> row to address (periodic wrap, else clamped)
+    auto rowp = [&](int r) -> int { return g.py ? wrap(r, g.ny) : min(max(r, 0), g.ny - 1); };
     auto load_u = [&](int r, double v[2]) {
-        bool ok;
-        const int rr = rowc(r, ok);
-        const uint32_t ob = (uint32_t)(rr * g.pitch + x) * (uint32_t)sizeof(double);
+        const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(double);
         v[0] = bload(rus, ob, 0u, 0.0);
         v[1] = bload(rus, ob, pbD, 0.0);
     };
     auto load_f = [&](int r, T f[9]) {
-        bool ok;
-        const int rr = rowc(r, ok);
-        const uint32_t ob = (uint32_t)(rr * g.pitch + xp) * (uint32_t)sizeof(T);
+        const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
         for (int q = 0; q < 9; q++)
             f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
     };
-    // the stores of one node: u (2 x FP64) and the nine populations
-    auto store_node = [&](uint32_t node, double vx, double vy, const T fn[9]) {
+    auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
         const uint32_t ou = node * (uint32_t)sizeof(double), of = node * (uint32_t)sizeof(T);
-        bstore(rud, ou, 0u, vx);
-        bstore(rud, ou, pbD, vy);
+        bstore(rud, ou, 0u, ux);
+        bstore(rud, ou, pbD, uy);
 #pragma unroll
         for (int q = 0; q < 9; q++)
             bstore(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
     };
-    // T = P(H) + Pi(H) at row r from u at rows r-1, r, r+1 of this lane
-    auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4]) {
-        const double lx = from_prev(u0[0]), rx = from_next(u0[0]);
-        const double ly = from_prev(u0[1]), ry = from_next(u0[1]);
-        bool ok;
-        const int rr = rowc(r, ok);
+    // one-sided differences at the lattice edges, central elsewhere
+    auto lo_row = [&](int r) { return !g.py && rowp(r) == 0 && r <= 0; };
+    auto hi_row = [&](int r) { return !g.py && rowp(r) == g.ny - 1 && r >= g.ny - 1; };
+
+    // T = P(H) + Pi(H) at row r of this lane; pl*/pr* replace the u of the
+    // column left of lane 0 / right of lane 63
+    auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4], double plx,
+                      double ply, double prx, double pry) {
+        double lx = from_prev(u0[0]), rx = from_next(u0[0]);
+        double ly = from_prev(u0[1]), ry = from_next(u0[1]);
+        lx = lane == 0 ? plx : lx;
+        ly = lane == 0 ? ply : ly;
+        rx = lane == 63 ? prx : rx;
+        ry = lane == 63 ? pry : ry;
         const double ax = atL ? u0[0] : lx, bx = atR ? u0[0] : rx;
         const double ay = atL ? u0[1] : ly, by = atR ? u0[1] : ry;
         const double fx = (atL || atR) ? idx : 0.5 * idx;
-        const bool lo = !g.py && rr == 0, hi = !g.py && rr == g.ny - 1;
+        const bool lo = lo_row(r), hi = hi_row(r);
         const double cx = lo ? u0[0] : um[0], dx = hi ? u0[0] : up[0];
         const double cy = lo ? u0[1] : um[1], dy = hi ? u0[1] : up[1];
         const double fy = (lo || hi) ? idx : 0.5 * idx;
-        T e[4];
         excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx), T((dy - cy) * fy),
-                              lam, mu, e);
-        const bool v = ok && xin;
-#pragma unroll
-        for (int c = 0; c < 4; c++) t[c] = v ? e[c] : T(0);
+                              lam, mu, t);
     };
-    // sigma = dt S / c at row r from T at rows r-1, r, r+1 of this lane
-    auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2]) {
-        const T lxx = from_prev(t0[0]), rxx = from_next(t0[0]);
-        const T lyx = from_prev(t0[2]), ryx = from_next(t0[2]);
-        bool ok;
-        const int rr = rowc(r, ok);
+    // sigma = dt S / c at row r of this lane; pl*/pr* replace T_xx, T_yx of the
+    // column left of lane 0 / right of lane 63
+    auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2], T plxx, T plyx, T prxx,
+                     T pryx) {
+        T lxx = from_prev(t0[0]), rxx = from_next(t0[0]);
+        T lyx = from_prev(t0[2]), ryx = from_next(t0[2]);
+        lxx = lane == 0 ? plxx : lxx;
+        lyx = lane == 0 ? plyx : lyx;
+        rxx = lane == 63 ? prxx : rxx;
+        ryx = lane == 63 ? pryx : ryx;
         const T axx = atL ? t0[0] : lxx, bxx = atR ? t0[0] : rxx;
         const T ayx = atL ? t0[2] : lyx, byx = atR ? t0[2] : ryx;
         const T fx = (atL || atR) ? T(1) : T(0.5);
-        const bool lo = !g.py && rr == 0, hi = !g.py && rr == g.ny - 1;
+        const bool lo = lo_row(r), hi = hi_row(r);
         const T cxy = lo ? t0[1] : tm[1], dxy = hi ? t0[1] : tp[1];
         const T cyy = lo ? t0[3] : tm[3], dyy = hi ? t0[3] : tp[3];
         const T fy = (lo || hi) ? T(1) : T(0.5);
-        const bool v = ok && xin;
-        const T s0 = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
-        const T s1 = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
-        sg[0] = v ? s0 : T(0);
-        sg[1] = v ? s1 : T(0);
+        sg[0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
+        sg[1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
     };
 
-    // Pipeline state at iteration r: u rows r..r+2 (U0..U2), T rows r, r+1,
-    // sigma rows r-1, r, populations rows r-1, r.  Two prefetch sets (A, B)
-    // alternate: the rows an iteration consumes were loaded two iterations
-    // earlier, so each wave keeps two rows of loads in flight.
+    // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
+    double gux[2], guy[2];
+    T gf;
+    auto gather = [&](int r0) {
+        const int i = min(lane, 5 * HK - 1);
+        const int c = i % 5, k = i / 5;
+        const int rr = rowp(r0 - 3 + k);
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++) {
+            const int hx = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
+            const uint32_t ob = (uint32_t)(rr * g.pitch + hx) * (uint32_t)sizeof(double);
+            gux[sd] = bload(rus, ob, 0u, 0.0);
+            guy[sd] = bload(rus, ob, pbD, 0.0);
+        }
+        const int j = min(lane, 47);
+        const int sd = j / 24, pi = (j % 24) / 8, k2 = 2 + j % 8;
+        const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
+        gf = fs[(size_t)halo_pop(sd, pi) * plane + (size_t)rowp(r0 - 3 + k2) * g.pitch + hx];
+    };
+    auto halo = [&](int r0) {
+        wave_lds_sync();  // the last block's reads come first
+        if (lane < 5 * HK) {
+            const int c = lane % 5, k = lane / 5;
+#pragma unroll
+            for (int sd = 0; sd < 2; sd++) {
+                hl.u[sd][k][c][0] = gux[sd];
+                hl.u[sd][k][c][1] = guy[sd];
+            }
+        }
+        wave_lds_sync();
+        if (lane < 60) {  // T at c = 1, 2, 3 and k = 1..10, both sides
+            const int sd = lane / 30, jj = lane % 30, c = 1 + jj % 3, k = 1 + jj / 3;
+            const int X = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
+            const int r = r0 - 3 + k;
+            const double u0x = hl.u[sd][k][c][0], u0y = hl.u[sd][k][c][1];
+            const bool aL = !g.px && X == 0, aR = !g.px && X == g.nx - 1;
+            const double ax = aL ? u0x : hl.u[sd][k][c - 1][0], bx = aR ? u0x : hl.u[sd][k][c + 1][0];
+            const double ay = aL ? u0y : hl.u[sd][k][c - 1][1], by = aR ? u0y : hl.u[sd][k][c + 1][1];
+            const double fx = (aL || aR) ? idx : 0.5 * idx;
+            const bool lo = lo_row(r), hi = hi_row(r);
+            const double cx = lo ? u0x : hl.u[sd][k - 1][c][0], dx = hi ? u0x : hl.u[sd][k + 1][c][0];
+            const double cy = lo ? u0y : hl.u[sd][k - 1][c][1], dy = hi ? u0y : hl.u[sd][k + 1][c][1];
+            const double fy = (lo || hi) ? idx : 0.5 * idx;
+            T t[4];
+            excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx), T((dy - cy) * fy),
+                                  lam, mu, t);
+#pragma unroll
+            for (int q = 0; q < 4; q++) hl.t[sd][k][c - 1][q] = t[q];
+        }
+        wave_lds_sync();
+        if (lane < 16) {  // sigma at c = 2 and k = 2..9
+            const int sd = lane / 8, k = 2 + lane % 8;
+            const int X = colp(sd == 0 ? x0 - 1 : x0 + 64);
+            const int r = r0 - 3 + k;
+            const bool aL = !g.px && X == 0, aR = !g.px && X == g.nx - 1;
+            const T t0xx = hl.t[sd][k][1][0], t0yx = hl.t[sd][k][1][2];
+            const T axx = aL ? t0xx : hl.t[sd][k][0][0], bxx = aR ? t0xx : hl.t[sd][k][2][0];
+            const T ayx = aL ? t0yx : hl.t[sd][k][0][2], byx = aR ? t0yx : hl.t[sd][k][2][2];
+            const T fx = (aL || aR) ? T(1) : T(0.5);
+            const bool lo = lo_row(r), hi = hi_row(r);
+            const T cxy = lo ? hl.t[sd][k][1][1] : hl.t[sd][k - 1][1][1];
+            const T dxy = hi ? hl.t[sd][k][1][1] : hl.t[sd][k + 1][1][1];
+            const T cyy = lo ? hl.t[sd][k][1][3] : hl.t[sd][k - 1][1][3];
+            const T dyy = hi ? hl.t[sd][k][1][3] : hl.t[sd][k + 1][1][3];
+            const T fy = (lo || hi) ? T(1) : T(0.5);
+            hl.s[sd][k][0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
+            hl.s[sd][k][1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
+        }
+        wave_lds_sync();
+        if (lane < 48) {  // pull sources: the population plus dt psi at the source
+            const int sd = lane / 24, pi = (lane % 24) / 8, k = 2 + lane % 8;
+            const int p = halo_pop(sd, pi);
+            hl.h[sd][k][pi] = gf + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
+        }
+        wave_lds_sync();
+    };
+
+    // ---- the row pipeline
+    // At iteration r the wave holds in registers the rows r..r+3 of u, r..r+2 of
+    // T, r-1..r+1 of sigma and r-1..r+1 of the populations, and the loads of the
+    // rows two iterations ahead are in flight (two prefetch sets A and B, so that
+    // no register holding a pending load is renamed).  x neighbours come from
+    // lane shuffles, y neighbours from the rows held; every iteration issues the
+    // same loads and stores in the same order, so the waits stay counted.
     double U0[2], U1[2], U2[2], tmp[2];
     T T0[4], T1[4];
     T Gm[2] = {T(0), T(0)}, G0[2] = {T(0), T(0)};
@@ -202,9 +295,8 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
 #pragma unroll
     for (int q = 0; q < 9; q++) zero9[q] = T(0);
 
-    // one iteration: consume the prefetched rows (u row r+3, populations row
-    // r+1), refill the set with the rows of iteration r+2, update row r
-    auto iteration = [&](int r, double Us[2], T Fs[9]) {
+    // iteration r of the block's relative row rel (0..HR-1)
+    auto iteration = [&](int r, int rel, double Us[2], T Fs[9]) {
         double U3[2] = {Us[0], Us[1]};
         T F1[9];
 #pragma unroll
@@ -212,10 +304,11 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
         load_u(r + 5, Us);
         load_f(r + 3, Fs);
         T T2[4], G1[2];
-        stress(r + 2, U1, U2, U3, T2);
-        sigma(r + 1, T0, T1, T2, G1);
+        stress(r + 2, U1, U2, U3, T2, hl.u[0][rel + 5][2][0], hl.u[0][rel + 5][2][1], hl.u[1][rel + 5][2][0],
+               hl.u[1][rel + 5][2][1]);
+        sigma(r + 1, T0, T1, T2, G1, hl.t[0][rel + 4][1][0], hl.t[0][rel + 4][1][2], hl.t[1][rel + 4][1][0],
+              hl.t[1][rel + 4][1][2]);
 
-        // pull f(t_{r+1}) at row r: the forcing dt psi is added at the source node
         T h[9];
         h[0] = F0[0];
         h[1] = F0[1] + T(3) * wq<T>(1) * G0[0];
@@ -228,14 +321,18 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
         h[8] = F1[8] + T(3) * wq<T>(8) * (G1[0] - G1[1]);
         T f[9];
         f[0] = h[0];
-        f[1] = from_prev(h[1]);
-        f[3] = from_next(h[3]);
         f[2] = h[2];
-        f[5] = from_prev(h[5]);
-        f[6] = from_next(h[6]);
         f[4] = h[4];
-        f[7] = from_next(h[7]);
-        f[8] = from_prev(h[8]);
+        {
+            const T f1 = from_prev(h[1]), f5 = from_prev(h[5]), f8 = from_prev(h[8]);
+            const T f3 = from_next(h[3]), f6 = from_next(h[6]), f7 = from_next(h[7]);
+            f[1] = lane == 0 ? hl.h[0][rel + 3][0] : f1;
+            f[5] = lane == 0 ? hl.h[0][rel + 2][1] : f5;
+            f[8] = lane == 0 ? hl.h[0][rel + 4][2] : f8;
+            f[3] = lane == 63 ? hl.h[1][rel + 3][0] : f3;
+            f[6] = lane == 63 ? hl.h[1][rel + 2][1] : f6;
+            f[7] = lane == 63 ? hl.h[1][rel + 4][2] : f7;
+        }
 
         T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
         T o1x = T(0), o1y = T(0);
@@ -250,7 +347,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
             if (ex(q)) o1x += T(ex(q)) * F0[q];
             if (ey(q)) o1y += T(ey(q)) * F0[q];
         }
-        const uint32_t node = (own && r >= yc && r < ye) ? (uint32_t)(r * g.pitch + x) : trash;
+        const uint32_t node = (r >= yc && r < ye) ? (uint32_t)(r * g.pitch + vx) : trash;
         T fn[9];
 #pragma unroll
         for (int q = 0; q < 9; q++) {
@@ -260,7 +357,6 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
         store_node(node, U0[0] + a.k.ucoef * (double)(m1x + o1x + G0[0]),
                    U0[1] + a.k.ucoef * (double)(m1y + o1y + G0[1]), fn);
 
-        // rotate the computed rows
         U0[0] = U1[0]; U0[1] = U1[1];
         U1[0] = U2[0]; U1[1] = U2[1];
         U2[0] = U3[0]; U2[1] = U3[1];
@@ -272,10 +368,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
         for (int q = 0; q < 9; q++) { Fm[q] = F0[q]; F0[q] = F1[q]; }
     };
 
-    // prime the pipeline for the first iteration r = yc - 2; the prefetch sets
-    // are loaded, each followed by the stores an iteration issues (to row ny),
-    // so that the loop is entered with its memory operations in the same order
-    // as from its back edge and the waits inside count alike on both paths
+    // prime: the halo of the first block (waited for here, once per chunk), the
+    // rows, the two prefetch sets each followed by the stores an iteration issues,
+    // and the gathers of the next block, in the order the loop repeats
+    int r0 = yc - 2;
+    gather(r0);
+    halo(r0);
     load_u(yc - 3, tmp);
     load_u(yc - 2, U0);
     load_u(yc - 1, U1);
@@ -286,15 +384,22 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
     load_u(yc + 2, UB);
     load_f(yc, FB);
     store_node(trash, 0.0, 0.0, zero9);
-    stress(yc - 2, tmp, U0, U1, T0);
-    stress(yc - 1, U0, U1, U2, T1);
+    gather(r0 + HR);
+    stress(yc - 2, tmp, U0, U1, T0, hl.u[0][3][2][0], hl.u[0][3][2][1], hl.u[1][3][2][0], hl.u[1][3][2][1]);
+    stress(yc - 1, U0, U1, U2, T1, hl.u[0][4][2][0], hl.u[0][4][2][1], hl.u[1][4][2][0], hl.u[1][4][2][1]);
 #pragma unroll
     for (int q = 0; q < 9; q++) { Fm[q] = T(0); F0[q] = T(0); }
 
-    // an even number of iterations from yc - 2; one past ye only writes row ny
-    for (int r = yc - 2; r < ye; r += 2) {
-        iteration(r, UA, FA);
-        iteration(r + 1, UB, FB);
+    for (int b = 0; b < nblk; b++) {
+        iteration(r0 + 0, 0, UA, FA);
+        iteration(r0 + 1, 1, UB, FB);
+        iteration(r0 + 2, 2, UA, FA);
+        iteration(r0 + 3, 3, UB, FB);
+        iteration(r0 + 4, 4, UA, FA);
+        iteration(r0 + 5, 5, UB, FB);
+        r0 += HR;
+        halo(r0);
+        gather(r0 + HR);
     }
 }
 
@@ -682,18 +787,20 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int n
 
 // ---- launchers ---------------------------------------------------------------------------------
 
-// rows per chunk of the marching kernel: enough waves to fill the chip twice
-// over, without letting the rows that prime each chunk dominate
+// rows per chunk of march_kernel: a multiple of HR minus the two priming
+// rows, with enough waves to fill the chip twice over
 static int march_chunk(const Geometry& g, int nstrip) {
     const long target = 16384;
     long c = ((long)g.ny * nstrip + target - 1) / target;
-    c = c < 8 ? 8 : (c > 128 ? 128 : c);
-    return (int)c;
+    long m = (c + 2 + HR - 1) / HR;
+    if (m < 1) m = 1;
+    if (m * HR - 2 > 190) m = (190 + 2) / HR;
+    return (int)(m * HR - 2);
 }
 
 template <typename T, int MAT>
 static void step_m(const StepArgs& a, hipStream_t st) {
-    const int nstrip = (a.g.nx + MO - 1) / MO;
+    const int nstrip = a.g.pitch / 64;
     const int chunk = march_chunk(a.g, nstrip);
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
     hipLaunchKernelGGL((march_kernel<T, MAT>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a, nstrip,
