@@ -3,13 +3,16 @@
 Workload: St. Venant-Kirchhoff uniaxial tension on an 8192 x 8192 D2Q9 lattice
 (mu = 0.05, nu = 0.3, tau = 0.55; left edge held, right edge pulled at
 3.2e-3 dx per step, top and bottom traction-free), synthetic and seeded.
-A step is one launch of the fused step kernel over the whole lattice; inputs
+A step is one launch of march_kernel over every node (walls included); inputs
 are resident in HBM before timing starts.  The headline value is MLUPS with
 FP32 population storage (FP64 displacement); the FP64 mode is reported beside
-it.  Prints one JSON line.
+it.  The roofline figures are those of march_kernel, timed with HIP events
+around each of its launches in the timed region.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode both|f32|f64]
                   [--n 8192] [--no-cpu-baseline]
+  python bench.py --ingest-counters FETCH_DIR WRITE_DIR   (no GPU: rocprofv3
+                  counter files -> profiles/step_kernel_traffic.json)
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_LUP = {"f32": 9 * 4 * 2 + 2 * 8 * 2, "f64": 9 * 8 * 2 + 2 * 8 * 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_00920_amd", "csrc", "mclbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+COPY_BYTES = 2 << 30  # bytes read (and written) by one launch of the calibration copy
 
 
 def kernel_hash() -> str:
@@ -68,8 +72,10 @@ def time_mode(mode: str, n: int, steps: int, warmup: int):
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
+    # the timed region: steps steps on the simulation's stream, with HIP events
+    # around each launch recorded by the library
     start.record(sim.stream)
-    sim.step(steps)
+    ms_kernel = sim.step_timed(steps)
     stop.record(sim.stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop)
@@ -77,13 +83,17 @@ def time_mode(mode: str, n: int, steps: int, warmup: int):
     nodes = n * n
     ms_step = ms / steps
     mlups = nodes * steps / (ms * 1e-3) / 1e6
-    achieved = BYTES_PER_LUP[mode] * nodes / (ms_step * 1e-3) / 1e9
+    # march_kernel reads and writes every node once per launch
+    alg_bytes = BYTES_PER_LUP[mode] * nodes
+    achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
     traffic = measured_traffic(mode, nodes)
     res = {
-        "value": mlups, "ms_per_step": ms_step,
+        "value": mlups, "ms_per_step": ms_step, "step_gbs": alg_bytes / (ms_step * 1e-3) / 1e9,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "bytes_per_lup": BYTES_PER_LUP[mode]},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic},
+        "kernels": {"march_kernel_ms": ms_kernel,
+                    "algorithmic_bytes_per_launch": alg_bytes,
+                    "traffic_vs_algorithmic": None if traffic is None else traffic / alg_bytes},
         "finite": not d["nonfinite"], "max_u": d["max_u"],
     }
     u = sim.read("u", host=False)
@@ -92,20 +102,22 @@ def time_mode(mode: str, n: int, steps: int, warmup: int):
     return res, u
 
 
-def copy_ceiling_gbs(nbytes: int = 4 << 30) -> float:
-    """Bandwidth of a plain elementwise copy (read + write) of nbytes."""
+def copy_ceiling_gbs(nbytes: int = COPY_BYTES) -> float:
+    """Bandwidth (read + write) of the library's plain copy kernel over nbytes."""
     import torch
-    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    from paper_2502_00920_amd import mclbm
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    st = torch.cuda.current_stream()
     for _ in range(3):
-        torch.mul(x, 1.0, out=y)
+        mclbm.mclbm_copy(y.data_ptr(), x.data_ptr(), nbytes, st.cuda_stream)
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
-    a.record()
+    a.record(st)
     for _ in range(reps):
-        torch.mul(x, 1.0, out=y)
-    b.record()
+        mclbm.mclbm_copy(y.data_ptr(), x.data_ptr(), nbytes, st.cuda_stream)
+    b.record(st)
     torch.cuda.synchronize()
     gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
     del x, y
@@ -141,6 +153,48 @@ def cpu_baseline(target_s: float = 15.0):
                       f"{threads} OpenMP threads on {platform.processor() or platform.machine()}"}
 
 
+def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE;
+    counter values in KiB per dispatch) into HBM bytes per launch of
+    march_kernel, each counter scaled by what it reads for the library's copy
+    kernel moving COPY_BYTES; writes TRAFFIC_FILE."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        vals = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path, newline="") as f:
+                for row in csv.DictReader(f):
+                    if row["Counter_Name"] != counter:
+                        continue
+                    name = row["Kernel_Name"]
+                    key = ("f32" if "mclbm::march_kernel<float, 0>" in name else
+                           "f64" if "mclbm::march_kernel<double, 0>" in name else
+                           "copy" if "mclbm::copy_kernel" in name else None)
+                    if key:
+                        vals.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
+        return {k: sum(v) / len(v) for k, v in vals.items()}
+
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    if "copy" not in fetch or "copy" not in write:
+        raise SystemExit("no copy_kernel dispatch in the counter files: cannot calibrate")
+    ff, fw = COPY_BYTES / fetch["copy"], COPY_BYTES / write["copy"]
+    out = {"kernel_hash": kernel_hash(), "workload": f"tension{n}", "copy_bytes": COPY_BYTES,
+           "fetch_factor": ff, "write_factor": fw}
+    for m in ("f32", "f64"):
+        if m in fetch and m in write:
+            rd, wr = fetch[m] * ff, write[m] * fw
+            alg = BYTES_PER_LUP[m] * n * n
+            out[m] = {"nodes": n * n, "fetch_size_bytes": fetch[m], "write_size_bytes": write[m],
+                      "read_bytes": rd, "written_bytes": wr, "bytes_per_launch": rd + wr,
+                      "algorithmic_bytes": alg, "ratio": (rd + wr) / alg}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,7 +203,12 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--mode", choices=["both", "f32", "f64"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic file from two rocprofv3 --pmc runs of this script and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters, args.n), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the time step of one "
               "lattice runs on a single MI355X; see DESIGN.md for how it would shard)", file=sys.stderr)
@@ -165,6 +224,7 @@ def main():
     for m in modes:
         results[m], fields[m] = time_mode(m, args.n, args.steps, args.warmup)
         print(f"# {m}: {results[m]['value']:.0f} MLUPS, {results[m]['ms_per_step']:.3f} ms/step, "
+              f"step {results[m]['step_gbs']:.0f} GB/s, march_kernel "
               f"{results[m]['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
     agree = None
     if "f32" in fields and "f64" in fields:
@@ -184,15 +244,16 @@ def main():
                                f"{args.n}x{args.n}, mu=0.05, nu=0.3, tau=0.55, left held, right "
                                "pulled 3.2e-3 dx/step, top/bottom traction-free",
                    "storage": "populations " + head + ", displacement f64"},
-        "hbm_gbs": r["roofline"]["achieved"],
-        "roofline": {k: v for k, v in r["roofline"].items() if k != "bytes_per_lup"},
+        "hbm_gbs": r["step_gbs"],
+        "roofline": r["roofline"],
+        "kernels": r["kernels"],
         "copy_ceiling_gbs": copy,
         "finite": r["finite"],
     }
     for m in modes[1:]:
         line[m] = {"value": results[m]["value"], "ms_per_step": results[m]["ms_per_step"],
-                   "hbm_gbs": results[m]["roofline"]["achieved"],
-                   "roofline": {k: v for k, v in results[m]["roofline"].items() if k != "bytes_per_lup"},
+                   "hbm_gbs": results[m]["step_gbs"],
+                   "roofline": results[m]["roofline"], "kernels": results[m]["kernels"],
                    "finite": results[m]["finite"]}
     if agree is not None:
         line["f32_vs_f64_rel_l2_u"] = agree

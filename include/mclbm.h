@@ -161,6 +161,19 @@ int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, int on_device);
 /* Advance nsteps >= 0 time steps, enqueued asynchronously on the stream. */
 int mclbm_step(mclbm_sim* s, int64_t nsteps);
 
+/* Advance nsteps (1..100000) time steps as mclbm_step does, with a HIP event
+ * recorded on the stream before each step's launch and after the last, and
+ * return the mean duration of one launch in milliseconds.  Synchronises the
+ * stream.  For measurement; the results equal those of mclbm_step bitwise. */
+int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step);
+
+/* Plain device copy of nbytes (a multiple of 4, buffers 4-byte aligned) from
+ * src to dst, enqueued on stream (a hipStream_t; NULL = null stream).  Not
+ * part of the method: the reference kernel of known traffic against which the
+ * hardware byte counters of the step kernels are calibrated, and the copy
+ * bandwidth they are compared with. */
+int mclbm_copy(void* dst, const void* src, size_t nbytes, void* stream);
+
 /* Number of steps taken since mclbm_init. */
 int64_t mclbm_stepno(const mclbm_sim* s);
 

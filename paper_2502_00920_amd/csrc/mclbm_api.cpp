@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "mclbm.h"
 #include "mclbm_internal.hpp"
@@ -302,24 +303,89 @@ MCLBM_EXPORT int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, in
     return MCLBM_OK;
 }
 
-MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
+namespace {
+
+StepArgs step_args(const mclbm_sim* s) {
+    StepArgs a;
+    a.fsrc = at(s, s->L.off_f[s->cur]);
+    a.fdst = at(s, s->L.off_f[1 - s->cur]);
+    a.usrc = static_cast<const double*>(at(s, s->L.off_u[s->cur]));
+    a.udst = static_cast<double*>(at(s, s->L.off_u[1 - s->cur]));
+    a.g = s->g;
+    a.k = s->k;
+    a.w = walls_at(s, s->n);
+    return a;
+}
+
+int check_steppable(const mclbm_sim* s, int64_t nsteps) {
     if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
-    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_step before mclbm_init");
+    if (!s->inited) return fail(MCLBM_ESTATE, "step before mclbm_init");
     if (nsteps < 0) return fail(MCLBM_EINVAL, "nsteps must be >= 0");
+    return MCLBM_OK;
+}
+
+}  // namespace
+
+MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
+    if (int e = check_steppable(s, nsteps)) return e;
     const int f64 = s->p.precision == MCLBM_F64;
     for (int64_t i = 0; i < nsteps; i++) {
-        StepArgs a;
-        a.fsrc = at(s, s->L.off_f[s->cur]);
-        a.fdst = at(s, s->L.off_f[1 - s->cur]);
-        a.usrc = static_cast<const double*>(at(s, s->L.off_u[s->cur]));
-        a.udst = static_cast<double*>(at(s, s->L.off_u[1 - s->cur]));
-        a.g = s->g;
-        a.k = s->k;
-        a.w = walls_at(s, s->n);
-        HIP_TRY(launch_step(f64, s->p.material, a, s->stream));
+        HIP_TRY(launch_step(f64, s->p.material, step_args(s), s->stream));
         s->cur = 1 - s->cur;
         s->n++;
     }
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step) {
+    if (int e = check_steppable(s, nsteps)) return e;
+    if (nsteps < 1 || nsteps > 100000) return fail(MCLBM_EINVAL, "nsteps must be in 1..100000");
+    if (!ms_per_step) return fail(MCLBM_EINVAL, "output pointer must not be NULL");
+    const int f64 = s->p.precision == MCLBM_F64;
+    // event i is recorded before the launch of step i, event nsteps after the last
+    std::vector<hipEvent_t> ev((size_t)(nsteps + 1), nullptr);
+    int rc = MCLBM_OK;
+    for (auto& e : ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            rc = fail(MCLBM_EHIP, "hipEventCreate failed");
+            break;
+        }
+    }
+    for (int64_t i = 0; rc == MCLBM_OK && i < nsteps; i++) {
+        hipError_t e = hipEventRecord(ev[i], s->stream);
+        if (e == hipSuccess) e = launch_step(f64, s->p.material, step_args(s), s->stream);
+        if (e != hipSuccess) {
+            rc = fail(MCLBM_EHIP, "step launch failed: %s", hipGetErrorString(e));
+            break;
+        }
+        s->cur = 1 - s->cur;
+        s->n++;
+    }
+    if (rc == MCLBM_OK && hipEventRecord(ev[nsteps], s->stream) != hipSuccess)
+        rc = fail(MCLBM_EHIP, "hipEventRecord failed");
+    if (rc == MCLBM_OK && hipStreamSynchronize(s->stream) != hipSuccess)
+        rc = fail(MCLBM_EHIP, "hipStreamSynchronize failed");
+    double total = 0;
+    for (int64_t k = 0; rc == MCLBM_OK && k < nsteps; k++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess)
+            rc = fail(MCLBM_EHIP, "hipEventElapsedTime failed");
+        total += ms;
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc != MCLBM_OK) return rc;
+    *ms_per_step = total / nsteps;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_copy(void* dst, const void* src, size_t nbytes, void* stream) {
+    if (nbytes % 4) return fail(MCLBM_EINVAL, "nbytes must be a multiple of 4");
+    if (nbytes && (!dst || !src)) return fail(MCLBM_EINVAL, "NULL buffer");
+    if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 4)
+        return fail(MCLBM_EINVAL, "buffers must be 4-byte aligned");
+    HIP_TRY(launch_copy(dst, src, nbytes / 4, static_cast<hipStream_t>(stream)));
     return MCLBM_OK;
 }
 

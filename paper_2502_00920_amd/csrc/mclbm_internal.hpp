@@ -40,7 +40,9 @@ struct ReadArgs {
     double* partial;   // diagnostics: 8 doubles per block
 };
 
+// one launch: march_kernel over every node, walls included
 hipError_t launch_step(int f64, int material, const StepArgs& a, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t n4, hipStream_t st);
 hipError_t launch_init(int f64, const InitArgs& a, hipStream_t st);
 hipError_t launch_read(int f64, int material, const ReadArgs& a, hipStream_t st);
 hipError_t launch_diag(int f64, int material, const ReadArgs& a, double* out, hipStream_t st);

@@ -15,10 +15,9 @@
 //      node's own post-collision populations and T_n(X)
 //   4. u_{n+1} = u_n + dt/(2 rho0) (j(t_{n+1}) + j(t_n)), both j carrying S_n
 //   5. fc'_{n+1} = (1 - omega) f + omega f_eq(r, M1, M2)
-// A step is two launches: march_kernel updates every node as an interior node
-// (one pass over HBM, each wave owning 64 aligned columns of a band of rows),
-// then wall_kernel recomputes the nodes on non-periodic walls (0.05 % of an
-// 8192^2 lattice) with the wall rules.
+// A step is one launch of march_kernel: one pass over HBM, each wave owning 64
+// aligned columns of a band of rows; the waves that touch a lattice edge apply
+// the wall rules to their wall nodes.
 // HBM traffic per node and step: 9 populations read and written, u read and
 // written (FP64): 176 B in FP64, 104 B in FP32 storage.
 #include "mclbm_internal.hpp"
@@ -58,34 +57,79 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t ob, ui
 __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, uint32_t ob, uint32_t so, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, ob, so, 0);
 }
+// Streaming stores (nt): the new state is read back only in the next step, long
+// after it has left the caches, so it should not displace the lines that the
+// halo reads of neighbouring strips reuse.
+constexpr int kCpolNT = 2;
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t ob, uint32_t so, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, ob, so, kCpolNT);
+}
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t ob, uint32_t so, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, ob, so, kCpolNT);
+}
 
+// ---- lane shifts across the wave (DPP wave_shr:1 / wave_shl:1, one VALU move per dword)
+
+constexpr int kDppWaveShr1 = 0x138;  // lane l reads lane l-1
+constexpr int kDppWaveShl1 = 0x130;  // lane l reads lane l+1
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double v, double edge) {
+    const u32x2 a = __builtin_bit_cast(u32x2, v), e = __builtin_bit_cast(u32x2, edge);
+    u32x2 r;
+    r.x = (unsigned)__builtin_amdgcn_update_dpp((int)e.x, (int)a.x, CTRL, 0xf, 0xf, false);
+    r.y = (unsigned)__builtin_amdgcn_update_dpp((int)e.y, (int)a.y, CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, r);
+}
+// value of lane l-1; lane 0 gets edge
 template <typename V>
-__device__ __forceinline__ V from_prev(V v) { return __shfl_up(v, 1); }    // value of lane l-1
+__device__ __forceinline__ V from_prev(V v, V edge) { return dpp_shift<kDppWaveShr1>(v, edge); }
+// value of lane l+1; lane 63 gets edge
 template <typename V>
-__device__ __forceinline__ V from_next(V v) { return __shfl_down(v, 1); }  // value of lane l+1
+__device__ __forceinline__ V from_next(V v, V edge) { return dpp_shift<kDppWaveShl1>(v, edge); }
 
 // ---- step: interior nodes, y-marching ------------------------------------------------------
 //
-// Each wave owns the 64 columns [64 s, 64 s + 64) of a strip, so that every
-// store covers whole cache lines (a partly written line costs a read-modify-
-// write in HBM).  The values lanes 0 and 63 need from the neighbouring columns
-// (u of x0-1 and x0+64, their T, and the pulled populations with their forcing)
-// come from a halo pass every HR rows: it gathers u on five columns per side,
-// computes T on three and sigma and the six pull sources on the neighbour
-// column, and leaves them in wave-private LDS (no barrier: only this wave reads
-// them).  The gathers of a halo pass are issued one block ahead.  Lanes beyond
-// nx compute on clamped (or, periodic, wrapped) data and store into the row
-// padding; rows that prime the pipeline store into row ny.
+// Each wave owns the 64 columns [x0, x0 + 64), x0 = 64 s, of a strip and marches
+// down a chunk of rows, so that every store covers whole cache lines (a partly
+// written line costs a read-modify-write in HBM).  At iteration r it holds in
+// registers the rows r..r+3 of u, r..r+2 of T, r-1..r+1 of sigma and r-1..r+1
+// of the populations, and the loads of the rows D iterations ahead are in
+// flight (D prefetch sets, so that no register holding a pending load is
+// renamed; every iteration issues the same loads and stores in the same order,
+// so the waits stay counted).  x neighbours come from lane shifts, y
+// neighbours from the rows held.
+//
+// What lanes 0 and 63 need from beyond the strip (u of x0-1 and x0+64, their
+// T, and the pulled populations with their forcing) comes from a halo pass
+// every HR rows: it gathers u on five columns per side, computes T on three,
+// sigma and the six pull sources on the neighbour column, and leaves them in
+// wave-private LDS (no barrier: only this wave reads them), where the lane
+// shifts take them as the value shifted in at the edge.  The gathers of a
+// halo pass are issued one block ahead.
+//
+// Waves whose rows and halo columns stay off the lattice edges (no clamping,
+// wrapping or one-sided differences) run a copy of the loop without those
+// selects.  Elsewhere, lanes beyond nx compute on clamped (or, periodic,
+// wrapped) data and store into the row padding; rows that prime the pipeline
+// store into row ny.
 
-constexpr int HR = 6;       // iterations per halo block
-constexpr int HK = HR + 6;  // halo rows per block: k = 0..HK-1 is row r0 - 3 + k
-
-template <typename T>
-struct Halo {
+template <typename T, int HR>
+struct Halo {  // rows k = 0..HR+5 of a block are rows r0 - 3 + k
+    static constexpr int HK = HR + 6;
     double u[2][HK][5][2];  // [side][k][column c][comp]; side 0: x0-3+c, side 1: x0+62+c
     T t[2][HK][3][4];       // T at c = 1, 2, 3
     T s[2][HK][2];          // sigma at c = 2
-    T h[2][HK][3];          // pull sources at c = 2: side 0 p = 1, 5, 8; side 1 p = 3, 6, 7
+    // what iteration rel of the block reads, side by side
+    double un[2][HR][2];    // u at c = 2, row r0 + rel + 2
+    T tn[2][HR][4];         // T at c = 2, row r0 + rel + 1
+    T hn[2][HR][4];         // pull sources at c = 2: side 0 p = 1, 5, 8 from rows
+                            // r0+rel, r0+rel-1, r0+rel+1; side 1 p = 3, 6, 7 likewise
 };
 
 // orders this wave's LDS writes before its later reads by other lanes (the
@@ -101,25 +145,36 @@ __device__ __forceinline__ int halo_pop(int side, int i) {
     return side == 0 ? (i == 0 ? 1 : (i == 1 ? 5 : 8)) : (i == 0 ? 3 : (i == 1 ? 6 : 7));
 }
 
-template <typename T, int MAT>
-__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
-    __shared__ Halo<T> halo_lds[4];
+template <bool B>
+struct Flag {
+    static constexpr bool value = B;
+};
+
+// HR: rows per halo block; D: rows of loads in flight (prefetch sets)
+template <typename T, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+    constexpr int HK = HR + 6;
+    constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);  // iterations per loop trip
+    constexpr int NU = 5 * HK, NT = 3 * (HK - 2), NS = HK - 4;         // halo items per side
+    static_assert(2 * NU <= 128 && NU <= 64 && 2 * NT <= 64 && 6 * NS <= 64 && HR >= 1 && D >= 1,
+                  "halo block too long for one wave");
+    __shared__ Halo<T, HR> halo_lds[4];
     const Geometry g = a.g;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    Halo<T>& hl = halo_lds[wv];
+    Halo<T, HR>& hl = halo_lds[wv];
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
     if (item >= nstrip * nchunk) return;
     const int strip = item % nstrip, chk = item / nstrip;
     const int x0 = strip * 64;
     const int vx = x0 + lane;  // this lane's column (< pitch)
-    // column -> column to address: periodic wrap, else clamped into the lattice
-    auto colp = [&](int c) -> int { return g.px ? wrap(c, g.nx) : min(max(c, 0), g.nx - 1); };
-    const int x = colp(vx);
-    const bool xin = g.px ? true : vx < g.nx;
-    const bool atL = xin && at_low(x, g.px), atR = xin && at_high(x, g.nx, g.px);
     const int yc = chk * chunk, ye = min(yc + chunk, g.ny);
-    const int nblk = (ye - (yc - 2) + HR - 1) / HR;
+    const int ntrip = (ye - (yc - 2) + L - 1) / L;
+    // rows and columns touched: rows yc-5 .. rmax, columns x0-3 .. x0+66
+    const int rmax = yc + ntrip * L + 2 * HR + D + 4;
+    const bool inner_y = g.py ? (yc - 5 >= 0 && rmax <= g.ny - 1) : (yc - 5 >= 1 && rmax <= g.ny - 2);
+    const bool inner_x = g.px ? (x0 >= 3 && x0 + 66 <= g.nx - 1) : (x0 >= 4 && x0 + 66 <= g.nx - 2);
+
     const size_t plane = (size_t)g.plane;
     const uint32_t pbT = (uint32_t)(plane * sizeof(T)), pbD = (uint32_t)(plane * sizeof(double));
     const T* fs = reinterpret_cast<const T*>(a.fsrc);
@@ -132,446 +187,421 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int nstrip, int 
     const double idx = a.k.inv_dx;
     const T ic2 = T(a.k.inv_c2), sbx = T(a.k.sig_b[0]), sby = T(a.k.sig_b[1]);
     const T lam = T(a.k.lam), mu = T(a.k.mu);
+    const T om = T(a.k.omega);
     const uint32_t trash = (uint32_t)(g.ny * g.pitch + vx);  // row ny: written, never read
 
-    // row r -> row to address (periodic wrap, else clamped)
-    auto rowp = [&](int r) -> int { return g.py ? wrap(r, g.ny) : min(max(r, 0), g.ny - 1); };
-    auto load_u = [&](int r, double v[2]) {
-        const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(double);
-        v[0] = bload(rus, ob, 0u, 0.0);
-        v[1] = bload(rus, ob, pbD, 0.0);
-    };
-    auto load_f = [&](int r, T f[9]) {
-        const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(T);
-#pragma unroll
-        for (int q = 0; q < 9; q++)
-            f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
-    };
-    auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
-        const uint32_t ou = node * (uint32_t)sizeof(double), of = node * (uint32_t)sizeof(T);
-        bstore(rud, ou, 0u, ux);
-        bstore(rud, ou, pbD, uy);
-#pragma unroll
-        for (int q = 0; q < 9; q++)
-            bstore(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
-    };
-    // one-sided differences at the lattice edges, central elsewhere
-    auto lo_row = [&](int r) { return !g.py && rowp(r) == 0 && r <= 0; };
-    auto hi_row = [&](int r) { return !g.py && rowp(r) == g.ny - 1 && r >= g.ny - 1; };
+    auto run = [&](auto edge_flag) {
+        constexpr bool EDGE = decltype(edge_flag)::value;
+        // row / column -> row / column to address: periodic wrap, else clamped
+        auto rowp = [&](int r) -> int {
+            if constexpr (EDGE) return g.py ? wrap(r, g.ny) : min(max(r, 0), g.ny - 1);
+            else return r;
+        };
+        auto colp = [&](int c) -> int {
+            if constexpr (EDGE) return g.px ? wrap(c, g.nx) : min(max(c, 0), g.nx - 1);
+            else return c;
+        };
+        const int x = colp(vx);
+        const bool xin = g.px || vx < g.nx;
+        const bool atL = EDGE && xin && at_low(x, g.px), atR = EDGE && xin && at_high(x, g.nx, g.px);
+        // one-sided differences at the lattice edges
+        auto lo_row = [&](int r) { return EDGE && !g.py && r <= 0; };
+        auto hi_row = [&](int r) { return EDGE && !g.py && r >= g.ny - 1; };
 
-    // T = P(H) + Pi(H) at row r of this lane; pl*/pr* replace the u of the
-    // column left of lane 0 / right of lane 63
-    auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4], double plx,
-                      double ply, double prx, double pry) {
-        double lx = from_prev(u0[0]), rx = from_next(u0[0]);
-        double ly = from_prev(u0[1]), ry = from_next(u0[1]);
-        lx = lane == 0 ? plx : lx;
-        ly = lane == 0 ? ply : ly;
-        rx = lane == 63 ? prx : rx;
-        ry = lane == 63 ? pry : ry;
-        const double ax = atL ? u0[0] : lx, bx = atR ? u0[0] : rx;
-        const double ay = atL ? u0[1] : ly, by = atR ? u0[1] : ry;
-        const double fx = (atL || atR) ? idx : 0.5 * idx;
-        const bool lo = lo_row(r), hi = hi_row(r);
-        const double cx = lo ? u0[0] : um[0], dx = hi ? u0[0] : up[0];
-        const double cy = lo ? u0[1] : um[1], dy = hi ? u0[1] : up[1];
-        const double fy = (lo || hi) ? idx : 0.5 * idx;
-        excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx), T((dy - cy) * fy),
-                              lam, mu, t);
-    };
-    // sigma = dt S / c at row r of this lane; pl*/pr* replace T_xx, T_yx of the
-    // column left of lane 0 / right of lane 63
-    auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2], T plxx, T plyx, T prxx,
-                     T pryx) {
-        T lxx = from_prev(t0[0]), rxx = from_next(t0[0]);
-        T lyx = from_prev(t0[2]), ryx = from_next(t0[2]);
-        lxx = lane == 0 ? plxx : lxx;
-        lyx = lane == 0 ? plyx : lyx;
-        rxx = lane == 63 ? prxx : rxx;
-        ryx = lane == 63 ? pryx : ryx;
-        const T axx = atL ? t0[0] : lxx, bxx = atR ? t0[0] : rxx;
-        const T ayx = atL ? t0[2] : lyx, byx = atR ? t0[2] : ryx;
-        const T fx = (atL || atR) ? T(1) : T(0.5);
-        const bool lo = lo_row(r), hi = hi_row(r);
-        const T cxy = lo ? t0[1] : tm[1], dxy = hi ? t0[1] : tp[1];
-        const T cyy = lo ? t0[3] : tm[3], dyy = hi ? t0[3] : tp[3];
-        const T fy = (lo || hi) ? T(1) : T(0.5);
-        sg[0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
-        sg[1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
-    };
-
-    // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
-    double gux[2], guy[2];
-    T gf;
-    auto gather = [&](int r0) {
-        const int i = min(lane, 5 * HK - 1);
-        const int c = i % 5, k = i / 5;
-        const int rr = rowp(r0 - 3 + k);
+        auto load_u = [&](int r, double v[2]) {
+            const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(double);
+            v[0] = bload(rus, ob, 0u, 0.0);
+            v[1] = bload(rus, ob, pbD, 0.0);
+        };
+        auto load_f = [&](int r, T f[9]) {
+            const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(T);
 #pragma unroll
-        for (int sd = 0; sd < 2; sd++) {
-            const int hx = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
-            const uint32_t ob = (uint32_t)(rr * g.pitch + hx) * (uint32_t)sizeof(double);
-            gux[sd] = bload(rus, ob, 0u, 0.0);
-            guy[sd] = bload(rus, ob, pbD, 0.0);
-        }
-        const int j = min(lane, 47);
-        const int sd = j / 24, pi = (j % 24) / 8, k2 = 2 + j % 8;
-        const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
-        gf = fs[(size_t)halo_pop(sd, pi) * plane + (size_t)rowp(r0 - 3 + k2) * g.pitch + hx];
-    };
-    auto halo = [&](int r0) {
-        wave_lds_sync();  // the last block's reads come first
-        if (lane < 5 * HK) {
-            const int c = lane % 5, k = lane / 5;
+            for (int q = 0; q < 9; q++)
+                f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
+        };
+        auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
+            const uint32_t ou = node * (uint32_t)sizeof(double), of = node * (uint32_t)sizeof(T);
+            bstore_nt(rud, ou, 0u, ux);
+            bstore_nt(rud, ou, pbD, uy);
+#pragma unroll
+            for (int q = 0; q < 9; q++)
+                bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
+        };
+
+        // T = P(H) + Pi(H) at row r of this lane; ul / ur: u of the columns left of
+        // lane 0 and right of lane 63
+        auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4],
+                          const double ul[2], const double ur[2]) {
+            double lx = from_prev(u0[0], ul[0]), rx = from_next(u0[0], ur[0]);
+            double ly = from_prev(u0[1], ul[1]), ry = from_next(u0[1], ur[1]);
+            double fx = 0.5 * idx, fy = 0.5 * idx;
+            double cx = um[0], dx = up[0], cy = um[1], dy = up[1];
+            if constexpr (EDGE) {
+                lx = atL ? u0[0] : lx;
+                ly = atL ? u0[1] : ly;
+                rx = atR ? u0[0] : rx;
+                ry = atR ? u0[1] : ry;
+                fx = (atL || atR) ? idx : fx;
+                const bool lo = lo_row(r), hi = hi_row(r);
+                cx = lo ? u0[0] : cx;
+                cy = lo ? u0[1] : cy;
+                dx = hi ? u0[0] : dx;
+                dy = hi ? u0[1] : dy;
+                fy = (lo || hi) ? idx : fy;
+            }
+            excess_stress<T, MAT>(T((rx - lx) * fx), T((dx - cx) * fy), T((ry - ly) * fx), T((dy - cy) * fy),
+                                  lam, mu, t);
+        };
+        // sigma = dt S / c at row r of this lane; tl / tr: T of the columns left of
+        // lane 0 and right of lane 63
+        auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2], const T tl[4],
+                         const T tr[4]) {
+            T lxx = from_prev(t0[0], tl[0]), rxx = from_next(t0[0], tr[0]);
+            T lyx = from_prev(t0[2], tl[2]), ryx = from_next(t0[2], tr[2]);
+            T fx = T(0.5), fy = T(0.5);
+            T cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3];
+            if constexpr (EDGE) {
+                lxx = atL ? t0[0] : lxx;
+                lyx = atL ? t0[2] : lyx;
+                rxx = atR ? t0[0] : rxx;
+                ryx = atR ? t0[2] : ryx;
+                fx = (atL || atR) ? T(1) : fx;
+                const bool lo = lo_row(r), hi = hi_row(r);
+                cxy = lo ? t0[1] : cxy;
+                cyy = lo ? t0[3] : cyy;
+                dxy = hi ? t0[1] : dxy;
+                dyy = hi ? t0[3] : dyy;
+                fy = (lo || hi) ? T(1) : fy;
+            }
+            sg[0] = ic2 * ((rxx - lxx) * fx + (dxy - cxy) * fy) + sbx;
+            sg[1] = ic2 * ((ryx - lyx) * fx + (dyy - cyy) * fy) + sby;
+        };
+
+        // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
+        double gu[2][2];  // u gathered for the next halo pass: [side][comp]
+        T gf;             // population gathered for it
+        auto gather_all = [&](int r0) {
+            const int i = min(lane, NU - 1);
+            const int c = i % 5, k = i / 5;
+            const int rr = rowp(r0 - 3 + k);
 #pragma unroll
             for (int sd = 0; sd < 2; sd++) {
-                hl.u[sd][k][c][0] = gux[sd];
-                hl.u[sd][k][c][1] = guy[sd];
+                const int hx = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
+                const uint32_t ob = (uint32_t)(rr * g.pitch + hx) * (uint32_t)sizeof(double);
+                gu[sd][0] = bload(rus, ob, 0u, 0.0);
+                gu[sd][1] = bload(rus, ob, pbD, 0.0);
+            }
+            const int j = min(lane, 6 * NS - 1);
+            const int sd = j / (3 * NS), pi = (j % (3 * NS)) / NS, k2 = 2 + j % NS;
+            const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
+            gf = fs[(size_t)halo_pop(sd, pi) * plane + (size_t)rowp(r0 - 3 + k2) * g.pitch + hx];
+        };
+        auto halo = [&](int r0) {
+            wave_lds_sync();  // the last block's reads come first
+            if (lane < NU) {
+                const int c = lane % 5, k = lane / 5;
+#pragma unroll
+                for (int sd = 0; sd < 2; sd++) {
+                    hl.u[sd][k][c][0] = gu[sd][0];
+                    hl.u[sd][k][c][1] = gu[sd][1];
+                    // u at c = 2 for the iteration that needs it: row r0 + rel + 2, k = rel + 5
+                    if (c == 2 && k >= 5 && k < 5 + HR) {
+                        hl.un[sd][k - 5][0] = gu[sd][0];
+                        hl.un[sd][k - 5][1] = gu[sd][1];
+                    }
+                }
+            }
+            wave_lds_sync();
+            if (lane < 2 * NT) {  // T at c = 1, 2, 3 and k = 1..HK-2, both sides
+                const int sd = lane / NT, jj = lane % NT, c = 1 + jj % 3, k = 1 + jj / 3;
+                const int X = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
+                const int r = r0 - 3 + k;
+                const double u0x = hl.u[sd][k][c][0], u0y = hl.u[sd][k][c][1];
+                const bool aL = EDGE && !g.px && X == 0, aR = EDGE && !g.px && X == g.nx - 1;
+                const double ax = aL ? u0x : hl.u[sd][k][c - 1][0], bx = aR ? u0x : hl.u[sd][k][c + 1][0];
+                const double ay = aL ? u0y : hl.u[sd][k][c - 1][1], by = aR ? u0y : hl.u[sd][k][c + 1][1];
+                const double fx = (aL || aR) ? idx : 0.5 * idx;
+                const bool lo = lo_row(r), hi = hi_row(r);
+                const double cx = lo ? u0x : hl.u[sd][k - 1][c][0], dx = hi ? u0x : hl.u[sd][k + 1][c][0];
+                const double cy = lo ? u0y : hl.u[sd][k - 1][c][1], dy = hi ? u0y : hl.u[sd][k + 1][c][1];
+                const double fy = (lo || hi) ? idx : 0.5 * idx;
+                T t[4];
+                excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx),
+                                      T((dy - cy) * fy), lam, mu, t);
+#pragma unroll
+                for (int q = 0; q < 4; q++) hl.t[sd][k][c - 1][q] = t[q];
+                // T at c = 2 for the iteration that needs it: row r0 + rel + 1, k = rel + 4
+                if (c == 2 && k >= 4 && k < 4 + HR) {
+#pragma unroll
+                    for (int q = 0; q < 4; q++) hl.tn[sd][k - 4][q] = t[q];
+                }
+            }
+            wave_lds_sync();
+            if (lane < 2 * NS) {  // sigma at c = 2 and k = 2..HK-3
+                const int sd = lane / NS, k = 2 + lane % NS;
+                const int X = colp(sd == 0 ? x0 - 1 : x0 + 64);
+                const int r = r0 - 3 + k;
+                const bool aL = EDGE && !g.px && X == 0, aR = EDGE && !g.px && X == g.nx - 1;
+                const T t0xx = hl.t[sd][k][1][0], t0yx = hl.t[sd][k][1][2];
+                const T axx = aL ? t0xx : hl.t[sd][k][0][0], bxx = aR ? t0xx : hl.t[sd][k][2][0];
+                const T ayx = aL ? t0yx : hl.t[sd][k][0][2], byx = aR ? t0yx : hl.t[sd][k][2][2];
+                const T fx = (aL || aR) ? T(1) : T(0.5);
+                const bool lo = lo_row(r), hi = hi_row(r);
+                const T cxy = lo ? hl.t[sd][k][1][1] : hl.t[sd][k - 1][1][1];
+                const T dxy = hi ? hl.t[sd][k][1][1] : hl.t[sd][k + 1][1][1];
+                const T cyy = lo ? hl.t[sd][k][1][3] : hl.t[sd][k - 1][1][3];
+                const T dyy = hi ? hl.t[sd][k][1][3] : hl.t[sd][k + 1][1][3];
+                const T fy = (lo || hi) ? T(1) : T(0.5);
+                hl.s[sd][k][0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
+                hl.s[sd][k][1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
+            }
+            wave_lds_sync();
+            if (lane < 6 * NS) {  // pull sources: the population plus dt psi at the source
+                const int sd = lane / (3 * NS), pi = (lane % (3 * NS)) / NS, k = 2 + lane % NS;
+                const int p = halo_pop(sd, pi);
+                const T hv = gf + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
+                // the iteration pulling it: p = 1, 3 from its own row (k = rel + 3),
+                // p = 5, 6 from the row before (k = rel + 2), p = 7, 8 from the row after
+                const int rel = k - (pi == 0 ? 3 : (pi == 1 ? 2 : 4));
+                if (rel >= 0 && rel < HR) hl.hn[sd][rel][pi] = hv;
+            }
+            wave_lds_sync();
+        };
+
+        // The links of a wall node whose source lies beyond a wall (Sect. 3.3), from
+        // the node's own populations fo, sigma g0 and T t0 at t_n: modified
+        // bounce-back (Eq. bbcon) across Dirichlet sides, modified anti-bounce-back
+        // (Eq. abbcon) across Neumann sides.  A link crossing a Dirichlet and a
+        // Neumann side takes the Dirichlet rule, one crossing two Dirichlet sides
+        // the mean of their j*, one crossing two Neumann sides the Pi_bd with both
+        // normal rows from the tractions and the mean of the two shear entries.
+        const bool has_xwall = EDGE && !g.px && (x0 == 0 || (g.nx - 1 >= x0 && g.nx - 1 < x0 + 64));
+        const bool lane_xwall = has_xwall && xin && (atL || atR);
+        const T sxw = atL ? T(-1) : T(1);  // outward normal of this lane's x wall
+        // that wall's data (selects between kernel arguments, no indexing by lane)
+        const bool dirx = atL ? a.w.bc[SIDE_L] == BC_DIR : a.w.bc[SIDE_R] == BC_DIR;
+        const double vxw0 = atL ? a.w.val[SIDE_L][0] : a.w.val[SIDE_R][0];
+        const double vxw1 = atL ? a.w.val[SIDE_L][1] : a.w.val[SIDE_R][1];
+        const T jxw0 = T(vxw0 * a.k.inv_c), jxw1 = T(vxw1 * a.k.inv_c);  // j*/c
+        const T c2i = T(a.k.inv_c2);
+        const T kxx = -sxw * T(vxw0 * a.k.inv_c2), kxy = -sxw * T(vxw1 * a.k.inv_c2);  // -n T*/c^2
+        // the rule value for the outgoing link q = (X, Y) of weight w, with the
+        // incoming link's post-collision value fcq and the moments M/c^2 of the wall
+        auto abb = [&](T fcq, T w, T X, T Y, T r0, T Mxx, T Mxy, T Myy) {
+            const T eMe = X * X * Mxx + T(2) * X * Y * Mxy + Y * Y * Myy;
+            const T e2 = X * X + Y * Y;
+            return -fcq + T(2) * w * (r0 + T(0.5) * (T(9) * eMe - T(3) * r0 * e2 - T(3) * (Mxx + Myy) + T(2) * r0));
+        };
+        auto r0_m2 = [&](const T fo[9], T& r0, T& mxx, T& myy) {
+            r0 = T(0); mxx = T(0); myy = T(0);  // the collision keeps r and Pi; psi has neither
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                r0 += fo[q];
+                if (ex(q)) mxx += fo[q];
+                if (ey(q)) myy += fo[q];
+            }
+        };
+        // links crossing only the x wall of this lane: p = (sx, 0), (sx, 1), (sx, -1),
+        // sx = -(outward normal); the outgoing link reflected is q = (-sx, -ey)
+        auto xwall_links = [&](const T fo[9], const T g0[2], const T t0[4], T f[9]) {
+            T r0, mxx, myy;
+            r0_m2(fo, r0, mxx, myy);
+            const T Mxx = kxx + t0[0] * c2i;
+            const T Mxy = kxy + t0[2] * c2i;
+            const T X = sxw;  // ex of the outgoing link
+            T v[3];
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                const T Y = k == 0 ? T(0) : (k == 1 ? T(-1) : T(1));  // ey of the outgoing link
+                const T w = k == 0 ? wq<T>(1) : wq<T>(5);
+                // q for the left wall: (-1, -ey) = 3, 7, 6; for the right wall: 1, 8, 5
+                const T foq = atL ? (k == 0 ? fo[3] : (k == 1 ? fo[7] : fo[6]))
+                                  : (k == 0 ? fo[1] : (k == 1 ? fo[8] : fo[5]));
+                const T fcq = foq + T(3) * w * (X * g0[0] + Y * g0[1]);
+                const T bb = fcq - T(6) * w * (X * jxw0 + Y * jxw1);
+                v[k] = dirx ? bb : abb(fcq, w, X, Y, r0, Mxx, Mxy, myy);
+            }
+            f[1] = atL ? v[0] : f[1];
+            f[5] = atL ? v[1] : f[5];
+            f[8] = atL ? v[2] : f[8];
+            f[3] = atR ? v[0] : f[3];
+            f[6] = atR ? v[1] : f[6];
+            f[7] = atR ? v[2] : f[7];
+        };
+        // links crossing the y wall of row 0 (onB) or ny-1, with the corner rules for
+        // those that cross an x wall too (wave-uniform: two rows per lattice)
+        auto ywall_links = [&](bool onB, const T fo[9], const T g0[2], const T t0[4], T f[9]) {
+            T r0, mxx, myy;
+            r0_m2(fo, r0, mxx, myy);
+            const T syw = onB ? T(-1) : T(1);
+            const bool diry = onB ? a.w.bc[SIDE_B] == BC_DIR : a.w.bc[SIDE_T] == BC_DIR;
+            const double vyw0 = onB ? a.w.val[SIDE_B][0] : a.w.val[SIDE_T][0];
+            const double vyw1 = onB ? a.w.val[SIDE_B][1] : a.w.val[SIDE_T][1];
+            const T Xxx = kxx + t0[0] * c2i;
+            const T Xxy = kxy + t0[2] * c2i;
+            const T Yyy = -syw * T(vyw1 * a.k.inv_c2) + t0[3] * c2i;
+            const T Yxy = -syw * T(vyw0 * a.k.inv_c2) + t0[1] * c2i;
+            const T jyw0 = T(vyw0 * a.k.inv_c), jyw1 = T(vyw1 * a.k.inv_c);
+#pragma unroll
+            for (int p = 1; p < 9; p++) {
+                if (ey(p) != (onB ? 1 : -1)) continue;  // links whose source is beyond the y wall
+                const bool crx = xin && ((atL && ex(p) > 0) || (atR && ex(p) < 0));
+                const int q = opp(p);
+                const T X = T(ex(q)), Y = T(ey(q)), w = wq<T>(q);
+                const T fcq = fo[q] + T(3) * w * (X * g0[0] + Y * g0[1]);
+                const bool dx_ = crx && dirx;
+                T jx = T(0), jy = T(0);
+                if (dx_) { jx += jxw0; jy += jxw1; }
+                if (diry) { jx += jyw0; jy += jyw1; }
+                const T bb = fcq - T(6) * w * (X * jx + Y * jy) / ((dx_ && diry) ? T(2) : T(1));
+                const T Mxx = crx ? Xxx : mxx;
+                const T Mxy = crx ? T(0.5) * (Xxy + Yxy) : Yxy;
+                const T ab = abb(fcq, w, X, Y, r0, Mxx, Mxy, Yyy);
+                f[p] = (dx_ || diry) ? bb : ab;
+            }
+        };
+
+        // ---- the row pipeline
+        double U0[2], U1[2], U2[2], tmp[2];
+        T T0[4], T1[4];
+        T Gm[2] = {T(0), T(0)}, G0[2] = {T(0), T(0)};
+        T Fm[9], F0[9];
+        // rows of loads in flight: the FP64 edge path keeps one, which leaves the
+        // registers its wall rules need (its waves are a few percent of the grid)
+        constexpr int DD = (EDGE && sizeof(T) == 8) ? 1 : D;
+        static_assert(L % DD == 0, "prefetch sets must divide the loop trip");
+        double UP[DD][2];
+        T FP[DD][9];
+        T zero9[9];
+#pragma unroll
+        for (int q = 0; q < 9; q++) zero9[q] = T(0);
+
+        // iteration r, the block's relative row rel (0..HR-1)
+        auto iteration = [&](int r, int rel, double Us[2], T Fs[9]) {
+            double U3[2] = {Us[0], Us[1]};
+            T F1[9];
+#pragma unroll
+            for (int q = 0; q < 9; q++) F1[q] = Fs[q];
+            load_u(r + 3 + DD, Us);
+            load_f(r + 1 + DD, Fs);
+            const double ul[2] = {hl.un[0][rel][0], hl.un[0][rel][1]};
+            const double ur[2] = {hl.un[1][rel][0], hl.un[1][rel][1]};
+            T T2[4], G1[2];
+            stress(r + 2, U1, U2, U3, T2, ul, ur);
+            T tl[4], tr[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                tl[q] = hl.tn[0][rel][q];
+                tr[q] = hl.tn[1][rel][q];
+            }
+            sigma(r + 1, T0, T1, T2, G1, tl, tr);
+
+            T h[9];
+            h[0] = F0[0];
+            h[1] = F0[1] + T(3) * wq<T>(1) * G0[0];
+            h[3] = F0[3] - T(3) * wq<T>(3) * G0[0];
+            h[2] = Fm[2] + T(3) * wq<T>(2) * Gm[1];
+            h[5] = Fm[5] + T(3) * wq<T>(5) * (Gm[0] + Gm[1]);
+            h[6] = Fm[6] + T(3) * wq<T>(6) * (Gm[1] - Gm[0]);
+            h[4] = F1[4] - T(3) * wq<T>(4) * G1[1];
+            h[7] = F1[7] - T(3) * wq<T>(7) * (G1[0] + G1[1]);
+            h[8] = F1[8] + T(3) * wq<T>(8) * (G1[0] - G1[1]);
+            T hL[4], hR[4];
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                hL[q] = hl.hn[0][rel][q];
+                hR[q] = hl.hn[1][rel][q];
+            }
+            T f[9];
+            f[0] = h[0];
+            f[2] = h[2];
+            f[4] = h[4];
+            f[1] = from_prev(h[1], hL[0]);
+            f[5] = from_prev(h[5], hL[1]);
+            f[8] = from_prev(h[8], hL[2]);
+            f[3] = from_next(h[3], hR[0]);
+            f[6] = from_next(h[6], hR[1]);
+            f[7] = from_next(h[7], hR[2]);
+            if constexpr (EDGE) {
+                if (has_xwall && lane_xwall) xwall_links(F0, G0, T0, f);
+                if (!g.py && (r == 0 || r == g.ny - 1)) ywall_links(r == 0, F0, G0, T0, f);
+            }
+
+            T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
+            T o1x = T(0), o1y = T(0);
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                rho += f[q];
+                if (ex(q)) m1x += T(ex(q)) * f[q];
+                if (ey(q)) m1y += T(ey(q)) * f[q];
+                if (ex(q)) m2xx += f[q];
+                if (ex(q) * ey(q)) m2xy += T(ex(q) * ey(q)) * f[q];
+                if (ey(q)) m2yy += f[q];
+                if (ex(q)) o1x += T(ex(q)) * F0[q];
+                if (ey(q)) o1y += T(ey(q)) * F0[q];
+            }
+            const uint32_t node = (r >= yc && r < ye) ? (uint32_t)(r * g.pitch + vx) : trash;
+            T fn[9];
+#pragma unroll
+            for (int q = 0; q < 9; q++) {
+                const T e = feq_q<T>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
+                fn[q] = f[q] + om * (e - f[q]);
+            }
+            store_node(node, U0[0] + a.k.ucoef * (double)(m1x + o1x + G0[0]),
+                       U0[1] + a.k.ucoef * (double)(m1y + o1y + G0[1]), fn);
+
+            U0[0] = U1[0]; U0[1] = U1[1];
+            U1[0] = U2[0]; U1[1] = U2[1];
+            U2[0] = U3[0]; U2[1] = U3[1];
+#pragma unroll
+            for (int c = 0; c < 4; c++) { T0[c] = T1[c]; T1[c] = T2[c]; }
+            Gm[0] = G0[0]; Gm[1] = G0[1];
+            G0[0] = G1[0]; G0[1] = G1[1];
+#pragma unroll
+            for (int q = 0; q < 9; q++) { Fm[q] = F0[q]; F0[q] = F1[q]; }
+        };
+
+        // prime: the halo of the first block (waited for here, once per chunk), the
+        // rows, the prefetch sets each followed by the stores an iteration issues,
+        // and the gathers of the next block, in the order the loop repeats
+        int r0 = yc - 2;
+        gather_all(r0);
+        halo(r0);
+        load_u(yc - 3, tmp);
+        load_u(yc - 2, U0);
+        load_u(yc - 1, U1);
+        load_u(yc, U2);
+#pragma unroll
+        for (int i = 0; i < DD; i++) {
+            load_u(yc + 1 + i, UP[i]);
+            load_f(yc - 1 + i, FP[i]);
+            store_node(trash, 0.0, 0.0, zero9);
+        }
+        gather_all(r0 + HR);
+        {
+            // T of the rows yc-2 (k = 3) and yc-1 (k = 4) of the first block
+            const double l3[2] = {hl.u[0][3][2][0], hl.u[0][3][2][1]}, r3[2] = {hl.u[1][3][2][0], hl.u[1][3][2][1]};
+            const double l4[2] = {hl.u[0][4][2][0], hl.u[0][4][2][1]}, r4[2] = {hl.u[1][4][2][0], hl.u[1][4][2][1]};
+            stress(yc - 2, tmp, U0, U1, T0, l3, r3);
+            stress(yc - 1, U0, U1, U2, T1, l4, r4);
+        }
+#pragma unroll
+        for (int q = 0; q < 9; q++) { Fm[q] = T(0); F0[q] = T(0); }
+
+        for (int b = 0; b < ntrip; b++) {
+#pragma unroll
+            for (int j = 0; j < L; j++) {
+                iteration(r0 + j % HR, j % HR, UP[j % DD], FP[j % DD]);
+                if (j % HR == HR - 1) {
+                    r0 += HR;
+                    halo(r0);
+                    gather_all(r0 + HR);
+                }
             }
         }
-        wave_lds_sync();
-        if (lane < 60) {  // T at c = 1, 2, 3 and k = 1..10, both sides
-            const int sd = lane / 30, jj = lane % 30, c = 1 + jj % 3, k = 1 + jj / 3;
-            const int X = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
-            const int r = r0 - 3 + k;
-            const double u0x = hl.u[sd][k][c][0], u0y = hl.u[sd][k][c][1];
-            const bool aL = !g.px && X == 0, aR = !g.px && X == g.nx - 1;
-            const double ax = aL ? u0x : hl.u[sd][k][c - 1][0], bx = aR ? u0x : hl.u[sd][k][c + 1][0];
-            const double ay = aL ? u0y : hl.u[sd][k][c - 1][1], by = aR ? u0y : hl.u[sd][k][c + 1][1];
-            const double fx = (aL || aR) ? idx : 0.5 * idx;
-            const bool lo = lo_row(r), hi = hi_row(r);
-            const double cx = lo ? u0x : hl.u[sd][k - 1][c][0], dx = hi ? u0x : hl.u[sd][k + 1][c][0];
-            const double cy = lo ? u0y : hl.u[sd][k - 1][c][1], dy = hi ? u0y : hl.u[sd][k + 1][c][1];
-            const double fy = (lo || hi) ? idx : 0.5 * idx;
-            T t[4];
-            excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx), T((dy - cy) * fy),
-                                  lam, mu, t);
-#pragma unroll
-            for (int q = 0; q < 4; q++) hl.t[sd][k][c - 1][q] = t[q];
-        }
-        wave_lds_sync();
-        if (lane < 16) {  // sigma at c = 2 and k = 2..9
-            const int sd = lane / 8, k = 2 + lane % 8;
-            const int X = colp(sd == 0 ? x0 - 1 : x0 + 64);
-            const int r = r0 - 3 + k;
-            const bool aL = !g.px && X == 0, aR = !g.px && X == g.nx - 1;
-            const T t0xx = hl.t[sd][k][1][0], t0yx = hl.t[sd][k][1][2];
-            const T axx = aL ? t0xx : hl.t[sd][k][0][0], bxx = aR ? t0xx : hl.t[sd][k][2][0];
-            const T ayx = aL ? t0yx : hl.t[sd][k][0][2], byx = aR ? t0yx : hl.t[sd][k][2][2];
-            const T fx = (aL || aR) ? T(1) : T(0.5);
-            const bool lo = lo_row(r), hi = hi_row(r);
-            const T cxy = lo ? hl.t[sd][k][1][1] : hl.t[sd][k - 1][1][1];
-            const T dxy = hi ? hl.t[sd][k][1][1] : hl.t[sd][k + 1][1][1];
-            const T cyy = lo ? hl.t[sd][k][1][3] : hl.t[sd][k - 1][1][3];
-            const T dyy = hi ? hl.t[sd][k][1][3] : hl.t[sd][k + 1][1][3];
-            const T fy = (lo || hi) ? T(1) : T(0.5);
-            hl.s[sd][k][0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
-            hl.s[sd][k][1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
-        }
-        wave_lds_sync();
-        if (lane < 48) {  // pull sources: the population plus dt psi at the source
-            const int sd = lane / 24, pi = (lane % 24) / 8, k = 2 + lane % 8;
-            const int p = halo_pop(sd, pi);
-            hl.h[sd][k][pi] = gf + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
-        }
-        wave_lds_sync();
     };
-
-    // ---- the row pipeline
-    // At iteration r the wave holds in registers the rows r..r+3 of u, r..r+2 of
-    // T, r-1..r+1 of sigma and r-1..r+1 of the populations, and the loads of the
-    // rows two iterations ahead are in flight (two prefetch sets A and B, so that
-    // no register holding a pending load is renamed).  x neighbours come from
-    // lane shuffles, y neighbours from the rows held; every iteration issues the
-    // same loads and stores in the same order, so the waits stay counted.
-    double U0[2], U1[2], U2[2], tmp[2];
-    T T0[4], T1[4];
-    T Gm[2] = {T(0), T(0)}, G0[2] = {T(0), T(0)};
-    T Fm[9], F0[9];
-    double UA[2], UB[2];
-    T FA[9], FB[9];
-    const T om = T(a.k.omega);
-    T zero9[9];
-#pragma unroll
-    for (int q = 0; q < 9; q++) zero9[q] = T(0);
-
-    // iteration r of the block's relative row rel (0..HR-1)
-    auto iteration = [&](int r, int rel, double Us[2], T Fs[9]) {
-        double U3[2] = {Us[0], Us[1]};
-        T F1[9];
-#pragma unroll
-        for (int q = 0; q < 9; q++) F1[q] = Fs[q];
-        load_u(r + 5, Us);
-        load_f(r + 3, Fs);
-        T T2[4], G1[2];
-        stress(r + 2, U1, U2, U3, T2, hl.u[0][rel + 5][2][0], hl.u[0][rel + 5][2][1], hl.u[1][rel + 5][2][0],
-               hl.u[1][rel + 5][2][1]);
-        sigma(r + 1, T0, T1, T2, G1, hl.t[0][rel + 4][1][0], hl.t[0][rel + 4][1][2], hl.t[1][rel + 4][1][0],
-              hl.t[1][rel + 4][1][2]);
-
-        T h[9];
-        h[0] = F0[0];
-        h[1] = F0[1] + T(3) * wq<T>(1) * G0[0];
-        h[3] = F0[3] - T(3) * wq<T>(3) * G0[0];
-        h[2] = Fm[2] + T(3) * wq<T>(2) * Gm[1];
-        h[5] = Fm[5] + T(3) * wq<T>(5) * (Gm[0] + Gm[1]);
-        h[6] = Fm[6] + T(3) * wq<T>(6) * (Gm[1] - Gm[0]);
-        h[4] = F1[4] - T(3) * wq<T>(4) * G1[1];
-        h[7] = F1[7] - T(3) * wq<T>(7) * (G1[0] + G1[1]);
-        h[8] = F1[8] + T(3) * wq<T>(8) * (G1[0] - G1[1]);
-        T f[9];
-        f[0] = h[0];
-        f[2] = h[2];
-        f[4] = h[4];
-        {
-            const T f1 = from_prev(h[1]), f5 = from_prev(h[5]), f8 = from_prev(h[8]);
-            const T f3 = from_next(h[3]), f6 = from_next(h[6]), f7 = from_next(h[7]);
-            f[1] = lane == 0 ? hl.h[0][rel + 3][0] : f1;
-            f[5] = lane == 0 ? hl.h[0][rel + 2][1] : f5;
-            f[8] = lane == 0 ? hl.h[0][rel + 4][2] : f8;
-            f[3] = lane == 63 ? hl.h[1][rel + 3][0] : f3;
-            f[6] = lane == 63 ? hl.h[1][rel + 2][1] : f6;
-            f[7] = lane == 63 ? hl.h[1][rel + 4][2] : f7;
-        }
-
-        T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
-        T o1x = T(0), o1y = T(0);
-#pragma unroll
-        for (int q = 0; q < 9; q++) {
-            rho += f[q];
-            if (ex(q)) m1x += T(ex(q)) * f[q];
-            if (ey(q)) m1y += T(ey(q)) * f[q];
-            if (ex(q)) m2xx += f[q];
-            if (ex(q) * ey(q)) m2xy += T(ex(q) * ey(q)) * f[q];
-            if (ey(q)) m2yy += f[q];
-            if (ex(q)) o1x += T(ex(q)) * F0[q];
-            if (ey(q)) o1y += T(ey(q)) * F0[q];
-        }
-        const uint32_t node = (r >= yc && r < ye) ? (uint32_t)(r * g.pitch + vx) : trash;
-        T fn[9];
-#pragma unroll
-        for (int q = 0; q < 9; q++) {
-            const T e = feq_q<T>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
-            fn[q] = f[q] + om * (e - f[q]);
-        }
-        store_node(node, U0[0] + a.k.ucoef * (double)(m1x + o1x + G0[0]),
-                   U0[1] + a.k.ucoef * (double)(m1y + o1y + G0[1]), fn);
-
-        U0[0] = U1[0]; U0[1] = U1[1];
-        U1[0] = U2[0]; U1[1] = U2[1];
-        U2[0] = U3[0]; U2[1] = U3[1];
-#pragma unroll
-        for (int c = 0; c < 4; c++) { T0[c] = T1[c]; T1[c] = T2[c]; }
-        Gm[0] = G0[0]; Gm[1] = G0[1];
-        G0[0] = G1[0]; G0[1] = G1[1];
-#pragma unroll
-        for (int q = 0; q < 9; q++) { Fm[q] = F0[q]; F0[q] = F1[q]; }
-    };
-
-    // prime: the halo of the first block (waited for here, once per chunk), the
-    // rows, the two prefetch sets each followed by the stores an iteration issues,
-    // and the gathers of the next block, in the order the loop repeats
-    int r0 = yc - 2;
-    gather(r0);
-    halo(r0);
-    load_u(yc - 3, tmp);
-    load_u(yc - 2, U0);
-    load_u(yc - 1, U1);
-    load_u(yc, U2);
-    load_u(yc + 1, UA);
-    load_f(yc - 1, FA);
-    store_node(trash, 0.0, 0.0, zero9);
-    load_u(yc + 2, UB);
-    load_f(yc, FB);
-    store_node(trash, 0.0, 0.0, zero9);
-    gather(r0 + HR);
-    stress(yc - 2, tmp, U0, U1, T0, hl.u[0][3][2][0], hl.u[0][3][2][1], hl.u[1][3][2][0], hl.u[1][3][2][1]);
-    stress(yc - 1, U0, U1, U2, T1, hl.u[0][4][2][0], hl.u[0][4][2][1], hl.u[1][4][2][0], hl.u[1][4][2][1]);
-#pragma unroll
-    for (int q = 0; q < 9; q++) { Fm[q] = T(0); F0[q] = T(0); }
-
-    for (int b = 0; b < nblk; b++) {
-        iteration(r0 + 0, 0, UA, FA);
-        iteration(r0 + 1, 1, UB, FB);
-        iteration(r0 + 2, 2, UA, FA);
-        iteration(r0 + 3, 3, UB, FB);
-        iteration(r0 + 4, 4, UA, FA);
-        iteration(r0 + 5, 5, UB, FB);
-        r0 += HR;
-        halo(r0);
-        gather(r0 + HR);
-    }
-}
-
-// ---- step: wall nodes ---------------------------------------------------------------------
-//
-// The nodes on non-periodic walls, one thread each, with global loads: the same
-// stresses and sources as march_kernel (same expressions, same precision) and
-// the wall rules of Sect. 3.3 for the links whose source lies beyond a wall.
-
-// the i-th wall node: bottom row, top row, then the left and right columns
-__device__ __forceinline__ bool wall_node(const Geometry& g, int i, int& x, int& y) {
-    int k = i;
-    if (!g.py) {
-        if (k < g.nx) { x = k; y = 0; return true; }
-        k -= g.nx;
-        if (k < g.nx) { x = k; y = g.ny - 1; return true; }
-        k -= g.nx;
-    }
-    if (!g.px) {
-        const int y0 = g.py ? 0 : 1, nyi = g.py ? g.ny : g.ny - 2;
-        if (k < nyi) { x = 0; y = y0 + k; return true; }
-        k -= nyi;
-        if (k < nyi) { x = g.nx - 1; y = y0 + k; return true; }
-    }
-    return false;
-}
-
-int wall_count(const Geometry& g) { return (g.py ? 0 : 2 * g.nx) + (g.px ? 0 : 2 * (g.py ? g.ny : g.ny - 2)); }
-
-__device__ __forceinline__ double ld_uc(const StepArgs& a, int c, int x, int y) {
-    return a.usrc[(size_t)c * a.g.plane + (size_t)y * a.g.pitch + x];
-}
-
-// T at an in-lattice node, as march_kernel's stress()
-template <typename T, int MAT>
-__device__ void wall_T(const StepArgs& a, int x, int y, T t[4]) {
-    const Geometry& g = a.g;
-    const double idx = a.k.inv_dx;
-    int xl = x - 1, xr = x + 1, yl = y - 1, yr = y + 1;
-    double fx = 0.5 * idx, fy = 0.5 * idx;
-    if (g.px) { xl = wrap1(xl, g.nx); xr = wrap1(xr, g.nx); }
-    else if (x == 0) { xl = x; fx = idx; }
-    else if (x == g.nx - 1) { xr = x; fx = idx; }
-    if (g.py) { yl = wrap1(yl, g.ny); yr = wrap1(yr, g.ny); }
-    else if (y == 0) { yl = y; fy = idx; }
-    else if (y == g.ny - 1) { yr = y; fy = idx; }
-    excess_stress<T, MAT>(T((ld_uc(a, 0, xr, y) - ld_uc(a, 0, xl, y)) * fx),
-                          T((ld_uc(a, 0, x, yr) - ld_uc(a, 0, x, yl)) * fy),
-                          T((ld_uc(a, 1, xr, y) - ld_uc(a, 1, xl, y)) * fx),
-                          T((ld_uc(a, 1, x, yr) - ld_uc(a, 1, x, yl)) * fy), T(a.k.lam), T(a.k.mu), t);
-}
-
-// sigma at an in-lattice node, as march_kernel's sigma()
-template <typename T, int MAT>
-__device__ void wall_sigma(const StepArgs& a, int x, int y, T sg[2]) {
-    const Geometry& g = a.g;
-    int xl = x - 1, xr = x + 1, yl = y - 1, yr = y + 1;
-    T fx = T(0.5), fy = T(0.5);
-    if (g.px) { xl = wrap1(xl, g.nx); xr = wrap1(xr, g.nx); }
-    else if (x == 0) { xl = x; fx = T(1); }
-    else if (x == g.nx - 1) { xr = x; fx = T(1); }
-    if (g.py) { yl = wrap1(yl, g.ny); yr = wrap1(yr, g.ny); }
-    else if (y == 0) { yl = y; fy = T(1); }
-    else if (y == g.ny - 1) { yr = y; fy = T(1); }
-    T tl[4], tr[4], tb[4], tt[4];
-    wall_T<T, MAT>(a, xl, y, tl);
-    wall_T<T, MAT>(a, xr, y, tr);
-    wall_T<T, MAT>(a, x, yl, tb);
-    wall_T<T, MAT>(a, x, yr, tt);
-    sg[0] = T(a.k.inv_c2) * ((tr[0] - tl[0]) * fx + (tt[1] - tb[1]) * fy) + T(a.k.sig_b[0]);
-    sg[1] = T(a.k.inv_c2) * ((tr[2] - tl[2]) * fx + (tt[3] - tb[3]) * fy) + T(a.k.sig_b[1]);
-}
-
-template <typename T, int MAT>
-__global__ __launch_bounds__(256) void wall_kernel(StepArgs a, int nwall) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    int x, y;
-    if (i >= nwall || !wall_node(a.g, i, x, y)) return;
-    const Geometry g = a.g;
-    const size_t plane = (size_t)g.plane;
-    const size_t o = (size_t)y * g.pitch + x;
-    const T* __restrict__ fs = reinterpret_cast<const T*>(a.fsrc);
-    T* __restrict__ fd = reinterpret_cast<T*>(a.fdst);
-    T fo[9];
-#pragma unroll
-    for (int q = 0; q < 9; q++) fo[q] = fs[q * plane + o];
-    T G0[2], T0[4];
-    wall_sigma<T, MAT>(a, x, y, G0);
-    wall_T<T, MAT>(a, x, y, T0);
-    const bool atL = at_low(x, g.px), atR = at_high(x, g.nx, g.px);
-    const bool onB = at_low(y, g.py), onT = at_high(y, g.ny, g.py);
-
-    // moments of the node's own populations at t_n (the collision keeps r and
-    // Pi, and psi has no zeroth or second moment)
-    double rr0 = 0, mxx = 0, myy = 0;
-#pragma unroll
-    for (int q = 0; q < 9; q++) {
-        rr0 += (double)fo[q];
-        mxx += (double)(ex(q) * ex(q)) * (double)fo[q];
-        myy += (double)(ey(q) * ey(q)) * (double)fo[q];
-    }
-    const int wx = atL ? SIDE_L : SIDE_R, wy = onB ? SIDE_B : SIDE_T;
-    const double sxw = atL ? -1.0 : 1.0, syw = onB ? -1.0 : 1.0;
-    const double c2i = a.k.inv_c2;
-    // Pi_bd / c^2 of the x wall and the y wall: normal row and column from the
-    // traction balance, tangential entry from the node
-    const double Xxx = (-sxw * a.w.val[wx][0] + (double)T0[0]) * c2i;
-    const double Xxy = (-sxw * a.w.val[wx][1] + (double)T0[2]) * c2i;
-    const double Yyy = (-syw * a.w.val[wy][1] + (double)T0[3]) * c2i;
-    const double Yxy = (-syw * a.w.val[wy][0] + (double)T0[1]) * c2i;
-
-    T f[9];
-#pragma unroll
-    for (int p = 0; p < 9; p++) {
-        int sxp = x - ex(p), syp = y - ey(p);
-        bool crx = false, cry = false;
-        if (g.px) sxp = wrap1(sxp, g.nx); else crx = sxp < 0 || sxp >= g.nx;
-        if (g.py) syp = wrap1(syp, g.ny); else cry = syp < 0 || syp >= g.ny;
-        if (!crx && !cry) {
-            T gs[2] = {G0[0], G0[1]};
-            if (p != 0) wall_sigma<T, MAT>(a, sxp, syp, gs);
-            f[p] = fs[p * plane + (size_t)syp * g.pitch + sxp] +
-                   T(3) * wq<T>(p) * (T(ex(p)) * gs[0] + T(ey(p)) * gs[1]);
-            continue;
-        }
-        const int q = opp(p);  // the outgoing link the wall reflects
-        const double fcq = (double)fo[q] + 3.0 * wq<double>(q) *
-                           ((double)ex(q) * (double)G0[0] + (double)ey(q) * (double)G0[1]);
-        double jx = 0.0, jy = 0.0;
-        int nd = 0;
-        if (crx && a.w.bc[wx] == BC_DIR) { jx += a.w.val[wx][0]; jy += a.w.val[wx][1]; nd++; }
-        if (cry && a.w.bc[wy] == BC_DIR) { jx += a.w.val[wy][0]; jy += a.w.val[wy][1]; nd++; }
-        double v;
-        if (nd > 0) {
-            // modified bounce-back, Eq. bbcon: -(2/cs^2) w c.j* = -6 w e.(j*/c)
-            const double sc = a.k.inv_c / (double)nd;
-            v = fcq - 6.0 * wq<double>(q) * ((double)ex(q) * jx + (double)ey(q) * jy) * sc;
-        } else {
-            // modified anti-bounce-back, Eq. abbcon
-            double Mxx, Mxy, Myy;
-            if (crx && cry) { Mxx = Xxx; Myy = Yyy; Mxy = 0.5 * (Xxy + Yxy); }
-            else if (crx) { Mxx = Xxx; Mxy = Xxy; Myy = myy; }
-            else { Mxx = mxx; Mxy = Yxy; Myy = Yyy; }
-            const double X = ex(q), Y = ey(q);
-            const double eMe = X * X * Mxx + 2.0 * X * Y * Mxy + Y * Y * Myy;
-            const double e2 = X * X + Y * Y;
-            v = -fcq + 2.0 * wq<double>(q) * (rr0 + 0.5 * (9.0 * eMe - 3.0 * rr0 * e2 - 3.0 * (Mxx + Myy) + 2.0 * rr0));
-        }
-        f[p] = T(v);
-    }
-
-    T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
-    T o1x = T(0), o1y = T(0);
-#pragma unroll
-    for (int q = 0; q < 9; q++) {
-        rho += f[q];
-        if (ex(q)) m1x += T(ex(q)) * f[q];
-        if (ey(q)) m1y += T(ey(q)) * f[q];
-        if (ex(q)) m2xx += f[q];
-        if (ex(q) * ey(q)) m2xy += T(ex(q) * ey(q)) * f[q];
-        if (ey(q)) m2yy += f[q];
-        if (ex(q)) o1x += T(ex(q)) * fo[q];
-        if (ey(q)) o1y += T(ey(q)) * fo[q];
-    }
-    a.udst[o] = a.usrc[o] + a.k.ucoef * (double)(m1x + o1x + G0[0]);
-    a.udst[plane + o] = a.usrc[plane + o] + a.k.ucoef * (double)(m1y + o1y + G0[1]);
-    const T om = T(a.k.omega);
-#pragma unroll
-    for (int q = 0; q < 9; q++) {
-        const T e = feq_q<T>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
-        fd[q * plane + o] = f[q] + om * (e - f[q]);
-    }
+    if (inner_x && inner_y) run(Flag<false>{});
+    else run(Flag<true>{});
 }
 
 // ---- per-node helpers for init, read-out and diagnostics (FP64, global loads) ----------
@@ -787,41 +817,72 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int n
 
 // ---- launchers ---------------------------------------------------------------------------------
 
-// rows per chunk of march_kernel: a multiple of HR minus the two priming
-// rows, with enough waves to fill the chip twice over
-static int march_chunk(const Geometry& g, int nstrip) {
+// rows per chunk of march_kernel: a multiple of its iterations per loop trip
+// minus the two priming rows, with enough waves to fill the chip twice over
+static int march_chunk(const Geometry& g, int nstrip, int L) {
     const long target = 16384;
     long c = ((long)g.ny * nstrip + target - 1) / target;
-    long m = (c + 2 + HR - 1) / HR;
+    long m = (c + 2 + L - 1) / L;
     if (m < 1) m = 1;
-    if (m * HR - 2 > 190) m = (190 + 2) / HR;
-    return (int)(m * HR - 2);
+    if (m * L - 2 > 190) m = (190 + 2) / L;
+    return (int)(m * L - 2);
+}
+
+template <typename T, int MAT, int HR, int D>
+static void launch_march(const StepArgs& a, hipStream_t st) {
+    constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);
+    const int nstrip = a.g.pitch / 64;
+    const int chunk = march_chunk(a.g, nstrip, L);
+    const int nchunk = (a.g.ny + chunk - 1) / chunk;
+    hipLaunchKernelGGL((march_kernel<T, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
+                       nstrip, nchunk, chunk);
 }
 
 template <typename T, int MAT>
-static void step_m(const StepArgs& a, hipStream_t st) {
-    const int nstrip = a.g.pitch / 64;
-    const int chunk = march_chunk(a.g, nstrip);
-    const int nchunk = (a.g.ny + chunk - 1) / chunk;
-    hipLaunchKernelGGL((march_kernel<T, MAT>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a, nstrip,
-                       nchunk, chunk);
-    const int nwall = wall_count(a.g);
-    if (nwall > 0)
-        hipLaunchKernelGGL((wall_kernel<T, MAT>), dim3((nwall + 255) / 256), dim3(256), 0, st, a, nwall);
+static hipError_t step_m(const StepArgs& a, hipStream_t st) {
+    // halo blocks of 6 rows, loads of 2 rows in flight: the fastest of the
+    // shapes measured on the 8192^2 workload (halo blocks of 2 to 6 rows, 2 or 3
+    // rows in flight), in FP32 and FP64
+    launch_march<T, MAT, 6, 2>(a, st);
+    return hipGetLastError();
 }
 
 template <typename T>
 static hipError_t step_t(int material, const StepArgs& a, hipStream_t st) {
     switch (material) {
-    case MAT_SVK: step_m<T, MAT_SVK>(a, st); break;
-    case MAT_NH: step_m<T, MAT_NH>(a, st); break;
-    default: step_m<T, MAT_LIN>(a, st); break;
+    case MAT_SVK: return step_m<T, MAT_SVK>(a, st);
+    case MAT_NH: return step_m<T, MAT_NH>(a, st);
+    default: return step_m<T, MAT_LIN>(a, st);
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_step(int f64, int material, const StepArgs& a, hipStream_t st) {
     return f64 ? step_t<double>(material, a, st) : step_t<float>(material, a, st);
+}
+
+// ---- plain copy: the reference kernel for hardware byte counters -------------------------------
+
+__global__ __launch_bounds__(256) void copy_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                   size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const float v0 = src[i], v1 = src[i + stride], v2 = src[i + 2 * stride], v3 = src[i + 3 * stride];
+        dst[i] = v0;
+        dst[i + stride] = v1;
+        dst[i + 2 * stride] = v2;
+        dst[i + 3 * stride] = v3;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t n4, hipStream_t st) {
+    if (n4 == 0) return hipSuccess;
+    size_t blocks = (n4 + 255) / 256;
+    if (blocks > 256 * 32) blocks = 256 * 32;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<const float*>(src),
+                       static_cast<float*>(dst), n4);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(int f64, const InitArgs& a, hipStream_t st) {

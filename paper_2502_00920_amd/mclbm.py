@@ -58,6 +58,8 @@ _sig = {
     "mclbm_set_side": (_i, [_vp, _i, C.POINTER(mclbm_side_spec)]),
     "mclbm_init": (_i, [_vp, _vp, _vp, _i]),
     "mclbm_step": (_i, [_vp, _i64]),
+    "mclbm_step_timed": (_i, [_vp, _i64, C.POINTER(C.c_double)]),
+    "mclbm_copy": (_i, [_vp, _vp, _sz, _vp]),
     "mclbm_stepno": (_i64, [_vp]),
     "mclbm_field_components": (_i, [_i]),
     "mclbm_read": (_i, [_vp, _i, _vp, _i]),
@@ -115,6 +117,17 @@ def mclbm_init(h: int, u0_ptr: Optional[int], j0_ptr: Optional[int], on_device: 
 
 def mclbm_step(h: int, nsteps: int) -> None:
     _check(_lib.mclbm_step(_vp(h), int(nsteps)), "mclbm_step")
+
+
+def mclbm_step_timed(h: int, nsteps: int) -> float:
+    """Mean ms of one step launch over nsteps steps, from HIP events around each."""
+    ms = C.c_double(0)
+    _check(_lib.mclbm_step_timed(_vp(h), int(nsteps), C.byref(ms)), "mclbm_step_timed")
+    return ms.value
+
+
+def mclbm_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> None:
+    _check(_lib.mclbm_copy(_vp(dst_ptr), _vp(src_ptr), int(nbytes), _vp(stream_ptr)), "mclbm_copy")
 
 
 def mclbm_stepno(h: int) -> int:
@@ -225,6 +238,10 @@ class Sim:
 
     def step(self, n: int = 1):
         mclbm_step(self._h, n)
+
+    def step_timed(self, n: int) -> float:
+        """Advance n steps; returns the mean ms of one step launch."""
+        return mclbm_step_timed(self._h, n)
 
     def read(self, field: str, host: bool = True):
         nc = mclbm_field_components(FIELD[field])

@@ -86,6 +86,9 @@ def test_host_side_errors_without_gpu(M):
             M.mclbm_step(h, 1)
         assert e.value.code == M.MCLBM_ESTATE
         with pytest.raises(M.MclbmError) as e:
+            M.mclbm_step_timed(h, 1)
+        assert e.value.code == M.MCLBM_ESTATE
+        with pytest.raises(M.MclbmError) as e:
             M.mclbm_read(h, 0, fake, 1)
         assert e.value.code == M.MCLBM_ESTATE
         with pytest.raises(M.MclbmError) as e:
@@ -110,3 +113,18 @@ def test_host_side_errors_without_gpu(M):
         assert M.mclbm_stepno(h) == 0
     finally:
         M.mclbm_destroy(h)
+
+
+def test_copy_argument_errors_without_gpu(M):
+    """mclbm_copy rejects bad sizes and pointers before any HIP call; zero bytes is a no-op."""
+    fake = 1 << 20
+    with pytest.raises(M.MclbmError) as e:
+        M.mclbm_copy(fake, fake + 4096, 6, 0)
+    assert e.value.code == M.MCLBM_EINVAL
+    with pytest.raises(M.MclbmError) as e:
+        M.mclbm_copy(fake + 2, fake + 4096, 8, 0)
+    assert e.value.code == M.MCLBM_EINVAL
+    with pytest.raises(M.MclbmError) as e:
+        M.mclbm_copy(None, fake, 8, 0)
+    assert e.value.code == M.MCLBM_EINVAL
+    M.mclbm_copy(None, None, 0, 0)

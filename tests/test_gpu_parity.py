@@ -258,7 +258,24 @@ def test_bitwise_determinism_and_checkpoint(M, precision):
     t.step(180)
     assert np.array_equal(t.read("u"), a)
     assert np.array_equal(a, runs[0])
+    # the timed stepping gives the same state bitwise
+    s = M.sim_from_workload(w, precision)
+    s.init(W.smooth_field(w.nx, w.ny, 0.02, seed=1))
+    ms = s.step_timed(300)
+    assert ms > 0 and s.n == 300
+    assert np.array_equal(s.read("u"), runs[0])
     del sides
+
+
+def test_copy_kernel(M):
+    print_case("calibration copy kernel")
+    import torch
+    x = torch.arange(3 * 1024 * 1024 + 5, dtype=torch.float32, device="cuda")
+    y = torch.zeros_like(x)
+    st = torch.cuda.current_stream()
+    M.mclbm_copy(y.data_ptr(), x.data_ptr(), x.numel() * 4, st.cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(x, y)
 
 
 def test_diag_parity(M):
