@@ -37,9 +37,9 @@ def rel(a, b):
 
 
 def pair(M, nx, ny, sides, *, material, mu=0.05, nu=0.3, tau=0.55, precision="f64", u0=None,
-         j0=None, rho0=1.0, dx=1.0, body=(0.0, 0.0)):
+         j0=None, rho0=1.0, dx=1.0, body=(0.0, 0.0), threads=THREADS):
     o = oracle.Oracle(nx, ny, mu=mu, nu=nu, tau=tau, material=material, rho0=rho0, dx=dx,
-                      body=body, threads=THREADS)
+                      body=body, threads=threads)
     s = M.Sim(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=precision, rho0=rho0,
               dx=dx, body=body)
     for side, spec in sides.items():
@@ -182,6 +182,30 @@ def test_tension1024(M, precision):
     w = W.tension_large(1024, 1000)
     for n, e, umax in run_workload(M, w, precision, [10, 30]):
         assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tension8192_full_size(M, precision):
+    """The benchmark lattice in the launch configuration bench.py times
+    (8192 x 8192, SVK, the tension walls), from a generic seeded state: every
+    node against the oracle after 1 and 3 steps."""
+    print_case(f"tension8192 full size {precision}")
+    w = W.tension_large(8192, 1000)
+    n = w.nx
+    u0 = W.smooth_field(n, n, 0.02, seed=11) + W.random_field(n, n, 1e-4, seed=12)
+    j0 = W.random_field(n, n, 1e-3, seed=13)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    o, s = pair(M, n, n, {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()},
+                material=w.material, mu=w.mu, nu=w.nu, tau=w.tau, precision=precision, u0=u0, j0=j0,
+                threads=max(1, min(16, cores)))
+    del u0, j0
+    for k in (1, 3):
+        o.step(k - o.n)
+        s.step(k - s.n)
+        e = compare(o, s, ("u", "p"))
+        print(k, {f: f"{v:.2e}" for f, v in e.items()}, flush=True)
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (k, e)
+    del o, s
 
 
 # ---- properties at size ----------------------------------------------------------------------
