@@ -9,7 +9,7 @@ FP32 population storage (FP64 displacement); the FP64 mode is reported beside
 it.  The roofline figures are those of march_kernel, timed with HIP events
 around each of its launches in the timed region.  Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode both|f32|f64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode all|f32|f64|f16|bf16]
                   [--n 8192] [--no-cpu-baseline]
   python bench.py --ingest-counters FETCH_DIR WRITE_DIR   (no GPU: rocprofv3
                   counter files -> profiles/step_kernel_traffic.json)
@@ -31,7 +31,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, published
 # algorithmic HBM bytes per lattice update: 9 populations read + written,
 # u (2 x FP64) read + written
-BYTES_PER_LUP = {"f32": 9 * 4 * 2 + 2 * 8 * 2, "f64": 9 * 8 * 2 + 2 * 8 * 2}
+BYTES_PER_LUP = {"f32": 9 * 4 * 2 + 2 * 8 * 2, "f64": 9 * 8 * 2 + 2 * 8 * 2,
+                 "f16": 9 * 2 * 2 + 2 * 8 * 2, "bf16": 9 * 2 * 2 + 2 * 8 * 2}
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_00920_amd", "csrc", "mclbm_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 COPY_BYTES = 2 << 30  # bytes read (and written) by one launch of the calibration copy
@@ -131,10 +132,10 @@ def copy_gbs(nbytes: int = COPY_BYTES) -> dict:
     return out
 
 
-def cpu_baseline(target_s: float = 15.0):
-    """The FP64 CPU oracle on the host cores: 1024 x 1024 subrun of the same
-    workload, as many steps as fit in about target_s seconds."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(n: int = 1024, steps: int = 1000):
+    """The FP64 CPU oracle on the host's cores over the n x n subrun of the
+    benchmark workload (all its steps).  Returns the baseline record and the
+    oracle's final u and P, the reference for the per-format subrun errors."""
     import oracle
     from paper_2502_00920_amd import workloads as W
 
@@ -142,21 +143,39 @@ def cpu_baseline(target_s: float = 15.0):
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         threads = min(threads or 1, int(os.environ["OMP_NUM_THREADS"]))
     threads = max(1, min(int(threads or 1), 64))
-    w = W.tension_large(1024, 1000)
+    w = W.tension_large(n, steps)
     o = oracle.Oracle(w.nx, w.ny, mu=w.mu, nu=w.nu, tau=w.tau, material=w.material, threads=threads)
     for side, sd in w.sides.items():
         o.set_side(side, sd.bc, sd.kind, sd.amp, sd.t0, sd.t1, sd.width)
     o.init()
     t0 = time.perf_counter()
-    o.step(10)
-    per = (time.perf_counter() - t0) / 10
-    k = max(2, min(2000, int(target_s / max(per, 1e-6))))
-    t0 = time.perf_counter()
-    o.step(k)
+    o.step(steps)
     dt = time.perf_counter() - t0
-    return {"value": w.nodes * k / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle, 1024x1024 SVK tension, {k} steps, {dt:.1f} s, "
-                      f"{threads} OpenMP threads on {platform.processor() or platform.machine()}"}
+    rec = {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+           "sample": f"FP64 oracle, {n}x{n} subrun of the SVK tension workload, all {steps} steps, "
+                     f"{dt:.1f} s, {threads} OpenMP threads on {platform.processor() or platform.machine()}"}
+    return rec, o.read("u"), o.read("p")
+
+
+def subrun_errors(u_ref, p_ref, n: int = 1024, steps: int = 1000) -> dict:
+    """Relative L2 error of u and P against the oracle's subrun, per storage format."""
+    import numpy as np
+    import torch
+    from paper_2502_00920_amd import mclbm
+    from paper_2502_00920_amd import workloads as W
+
+    w = W.tension_large(n, steps)
+    out = {"workload": f"tension{n}, {steps} steps (the subrun of the benchmark workload)"}
+    for m in ("f64", "f32", "f16", "bf16"):
+        sim = mclbm.sim_from_workload(w, precision=m)
+        sim.init()
+        sim.step(steps)
+        u, pk = sim.read("u"), sim.read("p")
+        out[m] = {"u": float(np.linalg.norm(u - u_ref) / np.linalg.norm(u_ref)),
+                  "p": float(np.linalg.norm(pk - p_ref) / np.linalg.norm(p_ref))}
+        del sim
+        torch.cuda.empty_cache()
+    return out
 
 
 def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
@@ -175,9 +194,10 @@ def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
                     if row["Counter_Name"] != counter:
                         continue
                     name = row["Kernel_Name"]
-                    # the workload's material is St. Venant-Kirchhoff (template argument 0)
-                    key = ("f32" if re.search(r"mclbm::march_kernel<float, 0\b", name) else
-                           "f64" if re.search(r"mclbm::march_kernel<double, 0\b", name) else
+                    # march_kernel<storage, material, ...>; the workload's material is
+                    # St. Venant-Kirchhoff (0)
+                    m = re.search(r"mclbm::march_kernel<(\d), 0\b", name)
+                    key = (("f64", "f32", "f16", "bf16")[int(m.group(1))] if m else
                            "copy" if "mclbm::copy_kernel" in name else None)
                     if key:
                         vals.setdefault(key, []).append(float(row["Counter_Value"]) * 1024.0)
@@ -189,7 +209,7 @@ def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
     ff, fw = COPY_BYTES / fetch["copy"], COPY_BYTES / write["copy"]
     out = {"kernel_hash": kernel_hash(), "workload": f"tension{n}", "copy_bytes": COPY_BYTES,
            "fetch_factor": ff, "write_factor": fw}
-    for m in ("f32", "f64"):
+    for m in ("f32", "f64", "f16", "bf16"):
         if m in fetch and m in write:
             rd, wr = fetch[m] * ff, write[m] * fw
             alg = BYTES_PER_LUP[m] * n * n
@@ -208,7 +228,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--mode", choices=["both", "f32", "f64"], default="both")
+    ap.add_argument("--mode", choices=["all", "f32", "f64", "f16", "bf16"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic file from two rocprofv3 --pmc runs of this script and exit")
@@ -226,7 +246,7 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
 
-    modes = ["f32", "f64"] if args.mode == "both" else [args.mode]
+    modes = ["f32", "f64", "f16", "bf16"] if args.mode == "all" else [args.mode]
     results, fields = {}, {}
     for m in modes:
         results[m], fields[m] = time_mode(m, args.n, args.steps, args.warmup)
@@ -234,9 +254,9 @@ def main():
               f"step {results[m]['step_gbs']:.0f} GB/s, march_kernel "
               f"{results[m]['roofline']['achieved']:.0f} GB/s", file=sys.stderr, flush=True)
     agree = None
-    if "f32" in fields and "f64" in fields:
-        a, b = fields["f32"], fields["f64"]
-        agree = float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    if "f64" in fields:
+        b = fields["f64"]
+        agree = {m: float(torch.linalg.norm(a - b) / torch.linalg.norm(b)) for m, a in fields.items() if m != "f64"}
     del fields
     torch.cuda.empty_cache()
     copy = copy_gbs()
@@ -262,10 +282,11 @@ def main():
                    "hbm_gbs": results[m]["step_gbs"],
                    "roofline": results[m]["roofline"], "kernels": results[m]["kernels"],
                    "finite": results[m]["finite"]}
-    if agree is not None:
-        line["f32_vs_f64_rel_l2_u"] = agree
+    if agree:
+        line["rel_l2_u_vs_f64_same_run"] = agree
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"], u_ref, p_ref = cpu_baseline()
+        line["subrun_error_vs_fp64_oracle"] = subrun_errors(u_ref, p_ref)
     print(json.dumps(line), flush=True)
 
 

@@ -52,10 +52,20 @@ enum mclbm_status {
 
 enum mclbm_material { MCLBM_SVK = 0, MCLBM_NEOHOOKE = 1, MCLBM_LINEAR = 2 };
 
-/* Storage and arithmetic of populations and stresses.  The displacement u is
- * integrated in FP64 in every mode; the boundary momentum-flux assembly of
- * Neumann walls is done in FP64 in every mode. */
-enum mclbm_precision { MCLBM_F64 = 0, MCLBM_F32 = 1 };
+/* Storage of the populations and the arithmetic of the step.  The displacement
+ * u is stored and integrated in FP64 in every mode, and its differences (the
+ * displacement gradient) are taken in FP64.
+ *   F64   populations FP64, arithmetic FP64 (the plain method)
+ *   F32   populations FP32, stresses, source, collision and wall rules in FP32
+ *   F16   populations stored as FP16, arithmetic FP32.  The rest state of the
+ *         scheme has f = 0, so the stored values are the deviations from that
+ *         equilibrium; they are kept times 2^(12 - floor(log2 rho0)), which
+ *         holds |f| from about 1.5e-8 rho0 to 16 rho0 in FP16's normal range
+ *   BF16  populations stored as BF16 (unscaled), arithmetic FP32
+ * The two 16-bit modes keep 18 bytes per node and buffer instead of 36 (F32)
+ * or 72 (F64).  Their error against F64 is reported per workload; no bound is
+ * claimed. */
+enum mclbm_precision { MCLBM_F64 = 0, MCLBM_F32 = 1, MCLBM_F16 = 2, MCLBM_BF16 = 3 };
 
 enum mclbm_side { MCLBM_LEFT = 0, MCLBM_RIGHT = 1, MCLBM_BOTTOM = 2, MCLBM_TOP = 3 };
 

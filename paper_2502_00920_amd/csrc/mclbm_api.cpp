@@ -49,12 +49,17 @@ struct Layout {
     size_t off_f[2], off_u[2], off_part, off_out, total;
 };
 
+// bytes per node of one population buffer: nine FP64 or FP32 values, or nine
+// 16-bit values (four planes of two per 32-bit word and one 16-bit plane)
+size_t pop_bytes_per_node(int precision) {
+    return precision == MCLBM_F64 ? 72 : (precision == MCLBM_F32 ? 36 : 18);
+}
+
 Layout layout_of(const mclbm_params& p) {
     Layout L;
     L.pitch = (p.nx + 63) / 64 * 64;
-    const size_t elem = p.precision == MCLBM_F64 ? 8 : 4;
-    const size_t plane = (size_t)(p.ny + 1) * L.pitch;  // row ny takes halo-lane stores
-    L.f_bytes = align_up(9 * plane * elem);
+    const size_t plane = (size_t)(p.ny + 1) * L.pitch;  // row ny takes the priming rows' stores
+    L.f_bytes = align_up(pop_bytes_per_node(p.precision) * plane);
     L.u_bytes = align_up(2 * plane * 8);
     Geometry g{p.nx, p.ny, L.pitch, 0, 0, (long long)plane};
     L.part_bytes = align_up((size_t)diag_blocks(g) * 8 * sizeof(double));
@@ -73,13 +78,16 @@ Layout layout_of(const mclbm_params& p) {
 int check_params(const mclbm_params* p) {
     if (!p) return fail(MCLBM_EINVAL, "params is NULL");
     if (p->nx < 3 || p->ny < 3) return fail(MCLBM_EINVAL, "nx and ny must be >= 3 (got %d x %d)", p->nx, p->ny);
-    // the device addresses three component planes through one 32-bit buffer range
+    if (p->precision < MCLBM_F64 || p->precision > MCLBM_BF16)
+        return fail(MCLBM_EINVAL, "unknown precision %d", p->precision);
+    // the device addresses three FP64 / FP32 planes, four planes of packed 16-bit
+    // pairs, or the two displacement planes through one 32-bit buffer range each
     {
         const int64_t plane = (int64_t)(p->ny + 1) * ((p->nx + 63) / 64 * 64);
-        const int64_t elem = p->precision == MCLBM_F64 ? 8 : 4;
-        if (plane * 3 * elem >= ((int64_t)1 << 32) || plane * 2 * 8 >= ((int64_t)1 << 32))
+        const int64_t range = p->precision == MCLBM_F64 ? 24 : (p->precision == MCLBM_F32 ? 12 : 16);
+        if (plane * range >= ((int64_t)1 << 32) || plane * 2 * 8 >= ((int64_t)1 << 32))
             return fail(MCLBM_EINVAL, "lattice of %d x %d nodes too large for one device buffer range "
-                        "(three planes must stay below 4 GiB)", p->nx, p->ny);
+                        "(the planes one range covers must stay below 4 GiB)", p->nx, p->ny);
     }
     if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
         return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");
@@ -87,8 +95,6 @@ int check_params(const mclbm_params* p) {
     if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(MCLBM_EINVAL, "nu must lie in (-1, 0.5) (got %g)", p->nu);
     if (p->material < MCLBM_SVK || p->material > MCLBM_LINEAR)
         return fail(MCLBM_EINVAL, "unknown material %d", p->material);
-    if (p->precision != MCLBM_F64 && p->precision != MCLBM_F32)
-        return fail(MCLBM_EINVAL, "unknown precision %d", p->precision);
     if (!std::isfinite(p->body[0]) || !std::isfinite(p->body[1]))
         return fail(MCLBM_EINVAL, "body force must be finite");
     return MCLBM_OK;
@@ -257,6 +263,11 @@ MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_b
     s->k.lam = 2.0 * p->mu * p->nu / (1.0 - 2.0 * p->nu);  // plane strain
     s->k.mu = p->mu;
     s->k.rho0 = p->rho0;
+    // FP16 storage keeps the populations times 2^(12 - floor(log2 rho0)): |f| up to
+    // about 16 rho0 stays below the FP16 maximum, and down to about 1.5e-8 rho0 in
+    // its normal range
+    s->k.fscale = p->precision == MCLBM_F16 ? std::ldexp(1.0, 12 - std::ilogb(p->rho0)) : 1.0;
+    s->k.finv = 1.0 / s->k.fscale;
     for (int i = 0; i < 4; i++) {
         std::memset(&s->side[i], 0, sizeof(mclbm_side_spec));
         s->side[i].bc = MCLBM_NEUMANN;
@@ -297,7 +308,8 @@ MCLBM_EXPORT int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, in
     a.j0 = stage;
     a.rho0 = s->p.rho0;
     a.inv_c = s->k.inv_c;
-    HIP_TRY(launch_init(s->p.precision == MCLBM_F64, a, s->stream));
+    a.fscale = s->k.fscale;
+    HIP_TRY(launch_init(s->p.precision, a, s->stream));
     s->n = 0;
     s->inited = true;
     return MCLBM_OK;
@@ -328,9 +340,8 @@ int check_steppable(const mclbm_sim* s, int64_t nsteps) {
 
 MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
     if (int e = check_steppable(s, nsteps)) return e;
-    const int f64 = s->p.precision == MCLBM_F64;
     for (int64_t i = 0; i < nsteps; i++) {
-        HIP_TRY(launch_step(f64, s->p.material, step_args(s), s->stream));
+        HIP_TRY(launch_step(s->p.precision, s->p.material, step_args(s), s->stream));
         s->cur = 1 - s->cur;
         s->n++;
     }
@@ -341,7 +352,6 @@ MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_s
     if (int e = check_steppable(s, nsteps)) return e;
     if (nsteps < 1 || nsteps > 100000) return fail(MCLBM_EINVAL, "nsteps must be in 1..100000");
     if (!ms_per_step) return fail(MCLBM_EINVAL, "output pointer must not be NULL");
-    const int f64 = s->p.precision == MCLBM_F64;
     // event i is recorded before the launch of step i, event nsteps after the last
     std::vector<hipEvent_t> ev((size_t)(nsteps + 1), nullptr);
     int rc = MCLBM_OK;
@@ -354,7 +364,7 @@ MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_s
     }
     for (int64_t i = 0; rc == MCLBM_OK && i < nsteps; i++) {
         hipError_t e = hipEventRecord(ev[i], s->stream);
-        if (e == hipSuccess) e = launch_step(f64, s->p.material, step_args(s), s->stream);
+        if (e == hipSuccess) e = launch_step(s->p.precision, s->p.material, step_args(s), s->stream);
         if (e != hipSuccess) {
             rc = fail(MCLBM_EHIP, "step launch failed: %s", hipGetErrorString(e));
             break;
@@ -415,8 +425,9 @@ MCLBM_EXPORT int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device)
     a.field = field;
     a.c = s->k.c;
     a.s_from_sig = s->k.s_from_sig;
+    a.finv = s->k.finv;
     a.partial = nullptr;
-    HIP_TRY(launch_read(s->p.precision == MCLBM_F64, s->p.material, a, s->stream));
+    HIP_TRY(launch_read(s->p.precision, s->p.material, a, s->stream));
     const size_t bytes = (size_t)nc * s->g.nx * s->g.ny * sizeof(double);
     if (!on_device) HIP_TRY(hipMemcpyAsync(dst, a.dst, bytes, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
@@ -434,9 +445,10 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
     a.field = 0;
     a.c = s->k.c;
     a.s_from_sig = s->k.s_from_sig;
+    a.finv = s->k.finv;
     a.partial = static_cast<double*>(at(s, s->L.off_part));
     double* dout = static_cast<double*>(at(s, s->L.off_out));
-    HIP_TRY(launch_diag(s->p.precision == MCLBM_F64, s->p.material, a, dout, s->stream));
+    HIP_TRY(launch_diag(s->p.precision, s->p.material, a, dout, s->stream));
     double h[5];
     HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));

@@ -37,6 +37,8 @@ struct Coef {
     double sig_b[2];  // rho0 b dX / c^2: body-force part of sigma
     double s_from_sig;// c / dt: S = sigma * c / dt
     double lam, mu, rho0;
+    double fscale;    // stored = population * fscale (a power of two; 1 except FP16 storage)
+    double finv;      // 1 / fscale
 };
 
 // Wall data of one step: type per side and its value at t_n (j* for
@@ -49,6 +51,9 @@ struct Walls {
 enum { SIDE_L = 0, SIDE_R = 1, SIDE_B = 2, SIDE_T = 3 };
 enum { BC_DIR = 0, BC_NEU = 1, BC_PER = 2 };
 enum { MAT_SVK = 0, MAT_NH = 1, MAT_LIN = 2 };
+// population storage: FP64, FP32, FP16 (scaled) or BF16; arithmetic is FP64 for
+// the first and FP32 for the others, the displacement FP64 always
+enum { PREC_F64 = 0, PREC_F32 = 1, PREC_F16 = 2, PREC_BF16 = 3 };
 
 // ---- D2Q9, Tab. 1 ---------------------------------------------------------------
 

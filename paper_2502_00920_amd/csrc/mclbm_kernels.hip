@@ -20,6 +20,8 @@
 // the wall rules to their wall nodes.
 // HBM traffic per node and step: 9 populations read and written, u read and
 // written (FP64): 176 B in FP64, 104 B in FP32 storage.
+#include <type_traits>
+
 #include "mclbm_internal.hpp"
 
 namespace mclbm {
@@ -66,6 +68,74 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t ob,
 }
 __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t ob, uint32_t so, double v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, ob, so, kCpolNT);
+}
+
+// ---- population storage formats ----------------------------------------------------------
+//
+// FP64 and FP32: nine planes of double / float.  FP16 and BF16: the populations two
+// per 32-bit word in four planes (word w holds population 2w in its low half and
+// 2w + 1 in its high half) and population 8 in a fifth plane of 16-bit values, 18
+// bytes per node.  In this scheme the rest state has f = 0, so the stored values
+// are the deviation from that equilibrium.  FP16 values are the populations times a
+// power of two (Coef::fscale) that keeps them out of the subnormal range; BF16 has
+// FP32's exponent range and is stored unscaled.  Arithmetic is FP32 for all three.
+
+__device__ __forceinline__ uint32_t f16_bits(float v) {
+    return __builtin_bit_cast(unsigned short, (_Float16)v);  // round to nearest even
+}
+__device__ __forceinline__ float f16_value(uint32_t b) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(b & 0xffffu));
+}
+__device__ __forceinline__ uint32_t bf16_bits(float v) {
+    return __builtin_bit_cast(unsigned short, (__bf16)v);  // round to nearest even (v_cvt_pk_bf16_f32)
+}
+__device__ __forceinline__ float bf16_value(uint32_t b) { return __builtin_bit_cast(float, (b & 0xffffu) << 16); }
+
+template <int PR>
+struct Store {  // PREC_F64, PREC_F32: plain planes
+    using T = typename std::conditional<PR == PREC_F64, double, float>::type;
+    static constexpr bool packed = false;
+};
+template <>
+struct Store<PREC_F16> {
+    using T = float;
+    static constexpr bool packed = true;
+    __device__ static uint32_t enc(float v) { return f16_bits(v); }
+    __device__ static float dec(uint32_t b) { return f16_value(b); }
+};
+template <>
+struct Store<PREC_BF16> {
+    using T = float;
+    static constexpr bool packed = true;
+    __device__ static uint32_t enc(float v) { return bf16_bits(v); }
+    __device__ static float dec(uint32_t b) { return bf16_value(b); }
+};
+
+// population q of the node at element offset o, for the per-node kernels
+template <int PR>
+__device__ __forceinline__ double pop_get(const void* f, size_t plane, size_t o, int q, double finv) {
+    using S = Store<PR>;
+    if constexpr (!S::packed) {
+        return (double)reinterpret_cast<const typename S::T*>(f)[(size_t)q * plane + o];
+    } else {
+        const uint32_t* w = reinterpret_cast<const uint32_t*>(f);
+        if (q == 8) return (double)S::dec(reinterpret_cast<const uint16_t*>(w + 4 * plane)[o]) * finv;
+        const uint32_t v = w[(size_t)(q >> 1) * plane + o];
+        return (double)S::dec((q & 1) ? (v >> 16) : v) * finv;
+    }
+}
+template <int PR>
+__device__ __forceinline__ void pop_put_all(void* f, size_t plane, size_t o, const double v[9], double fscale) {
+    using S = Store<PR>;
+    if constexpr (!S::packed) {
+        for (int q = 0; q < 9; q++) reinterpret_cast<typename S::T*>(f)[(size_t)q * plane + o] = (typename S::T)v[q];
+    } else {
+        uint32_t* w = reinterpret_cast<uint32_t*>(f);
+        for (int k = 0; k < 4; k++)
+            w[(size_t)k * plane + o] =
+                S::enc((float)(v[2 * k] * fscale)) | (S::enc((float)(v[2 * k + 1] * fscale)) << 16);
+        reinterpret_cast<uint16_t*>(w + 4 * plane)[o] = (uint16_t)S::enc((float)(v[8] * fscale));
+    }
 }
 
 // ---- lane shifts across the wave (DPP wave_shr:1 / wave_shl:1, one VALU move per dword)
@@ -150,9 +220,16 @@ struct Flag {
     static constexpr bool value = B;
 };
 
-// HR: rows per halo block; D: rows of loads in flight (prefetch sets)
-template <typename T, int MAT, int HR, int D>
+// PR: population storage; HR: rows per halo block; D: rows of loads in flight
+// (prefetch sets)
+template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+    using SF = Store<PR>;
+    using T = typename SF::T;  // arithmetic type
+    constexpr bool PK = SF::packed;
+    // a row of one lane's populations as loaded: nine values, or five packed words
+    using Raw = typename std::conditional<PK, uint32_t, T>::type;
+    constexpr int NRAW = PK ? 5 : 9;
     constexpr int HK = HR + 6;
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);  // iterations per loop trip
     constexpr int NU = 5 * HK, NT = 3 * (HK - 2), NS = HK - 4;         // halo items per side
@@ -176,14 +253,20 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
     const bool inner_x = g.px ? (x0 >= 3 && x0 + 66 <= g.nx - 1) : (x0 >= 4 && x0 + 66 <= g.nx - 2);
 
     const size_t plane = (size_t)g.plane;
-    const uint32_t pbT = (uint32_t)(plane * sizeof(T)), pbD = (uint32_t)(plane * sizeof(double));
-    const T* fs = reinterpret_cast<const T*>(a.fsrc);
-    T* fd = reinterpret_cast<T*>(a.fdst);
-    const __amdgpu_buffer_rsrc_t rs0 = rsrc(fs, 3 * pbT), rs1 = rsrc(fs + 3 * plane, 3 * pbT),
-                                 rs2 = rsrc(fs + 6 * plane, 3 * pbT);
-    const __amdgpu_buffer_rsrc_t rd0 = rsrc(fd, 3 * pbT), rd1 = rsrc(fd + 3 * plane, 3 * pbT),
-                                 rd2 = rsrc(fd + 6 * plane, 3 * pbT);
+    const uint32_t pbD = (uint32_t)(plane * sizeof(double));
+    // bytes per plane: of T (three planes per resource), or of 32-bit words (four
+    // planes in one resource, the 16-bit plane in another)
+    const uint32_t pbT = (uint32_t)(plane * (PK ? 4 : sizeof(T)));
+    const char* fs = reinterpret_cast<const char*>(a.fsrc);
+    char* fd = reinterpret_cast<char*>(a.fdst);
+    const __amdgpu_buffer_rsrc_t rs0 = rsrc(fs, (PK ? 4 : 3) * pbT),
+                                 rs1 = rsrc(fs + (PK ? 4 : 3) * (size_t)pbT, PK ? pbT / 2 : 3 * pbT),
+                                 rs2 = rsrc(fs + 6 * (size_t)pbT, PK ? 0 : 3 * pbT);
+    const __amdgpu_buffer_rsrc_t rd0 = rsrc(fd, (PK ? 4 : 3) * pbT),
+                                 rd1 = rsrc(fd + (PK ? 4 : 3) * (size_t)pbT, PK ? pbT / 2 : 3 * pbT),
+                                 rd2 = rsrc(fd + 6 * (size_t)pbT, PK ? 0 : 3 * pbT);
     const __amdgpu_buffer_rsrc_t rus = rsrc(a.usrc, 2 * pbD), rud = rsrc(a.udst, 2 * pbD);
+    const T finv = T(a.k.finv), fscl = T(a.k.fscale);
     const double idx = a.k.inv_dx;
     const T ic2 = T(a.k.inv_c2), sbx = T(a.k.sig_b[0]), sby = T(a.k.sig_b[1]);
     const T lam = T(a.k.lam), mu = T(a.k.mu);
@@ -213,19 +296,53 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
             v[0] = bload(rus, ob, 0u, 0.0);
             v[1] = bload(rus, ob, pbD, 0.0);
         };
-        auto load_f = [&](int r, T f[9]) {
-            const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(T);
+        // a row of populations as loaded (decoded only when consumed, so that the
+        // loads stay in flight)
+        auto load_f = [&](int r, Raw f[NRAW]) {
+            const uint32_t o = (uint32_t)(rowp(r) * g.pitch + x);
+            if constexpr (PK) {
 #pragma unroll
-            for (int q = 0; q < 9; q++)
-                f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
+                for (int w = 0; w < 4; w++)
+                    f[w] = __builtin_amdgcn_raw_buffer_load_b32(rs0, o * 4u, (uint32_t)w * pbT, 0);
+                f[4] = __builtin_amdgcn_raw_buffer_load_b16(rs1, o * 2u, 0u, 0);
+            } else {
+                const uint32_t ob = o * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int q = 0; q < 9; q++)
+                    f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
+            }
+        };
+        auto decode = [&](const Raw f[NRAW], T F[9]) {
+            if constexpr (PK) {
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    F[2 * w] = SF::dec(f[w]) * finv;
+                    F[2 * w + 1] = SF::dec(f[w] >> 16) * finv;
+                }
+                F[8] = SF::dec(f[4]) * finv;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 9; q++) F[q] = f[q];
+            }
         };
         auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
-            const uint32_t ou = node * (uint32_t)sizeof(double), of = node * (uint32_t)sizeof(T);
+            const uint32_t ou = node * (uint32_t)sizeof(double);
             bstore_nt(rud, ou, 0u, ux);
             bstore_nt(rud, ou, pbD, uy);
+            if constexpr (PK) {
 #pragma unroll
-            for (int q = 0; q < 9; q++)
-                bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
+                for (int w = 0; w < 4; w++)
+                    __builtin_amdgcn_raw_buffer_store_b32(
+                        SF::enc(fn[2 * w] * fscl) | (SF::enc(fn[2 * w + 1] * fscl) << 16), rd0, node * 4u,
+                        (uint32_t)w * pbT, kCpolNT);
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)SF::enc(fn[8] * fscl), rd1, node * 2u, 0u,
+                                                      kCpolNT);
+            } else {
+                const uint32_t of = node * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int q = 0; q < 9; q++)
+                    bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
+            }
         };
 
         // T = P(H) + Pi(H) at row r of this lane; ul / ur: u of the columns left of
@@ -279,7 +396,16 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
 
         // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
         double gu[2][2];  // u gathered for the next halo pass: [side][comp]
-        T gf;             // population gathered for it
+        Raw gf;           // population gathered for it (raw; packed: the word holding it)
+        // where this lane's halo population sits in a packed word: the high half?
+        // (population 8: the parity of its column, as the row pitch is even)
+        const bool ghigh = [&] {
+            const int j = min(lane, 6 * NS - 1);
+            const int sd = j / (3 * NS);
+            const int p = halo_pop(sd, (j % (3 * NS)) / NS);
+            const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
+            return p == 8 ? (hx & 1) != 0 : (p & 1) != 0;
+        }();
         auto gather_all = [&](int r0) {
             const int i = min(lane, NU - 1);
             const int c = i % 5, k = i / 5;
@@ -294,7 +420,15 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
             const int j = min(lane, 6 * NS - 1);
             const int sd = j / (3 * NS), pi = (j % (3 * NS)) / NS, k2 = 2 + j % NS;
             const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
-            gf = fs[(size_t)halo_pop(sd, pi) * plane + (size_t)rowp(r0 - 3 + k2) * g.pitch + hx];
+            const int p = halo_pop(sd, pi);
+            const size_t o = (size_t)rowp(r0 - 3 + k2) * g.pitch + hx;
+            if constexpr (PK) {
+                // population 8 from the 32-bit word of its 16-bit plane that holds it
+                const uint32_t* w = reinterpret_cast<const uint32_t*>(fs);
+                gf = p == 8 ? w[4 * plane + (o >> 1)] : w[(size_t)(p >> 1) * plane + o];
+            } else {
+                gf = reinterpret_cast<const T*>(fs)[(size_t)p * plane + o];
+            }
         };
         auto halo = [&](int r0) {
             wave_lds_sync();  // the last block's reads come first
@@ -359,7 +493,10 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
             if (lane < 6 * NS) {  // pull sources: the population plus dt psi at the source
                 const int sd = lane / (3 * NS), pi = (lane % (3 * NS)) / NS, k = 2 + lane % NS;
                 const int p = halo_pop(sd, pi);
-                const T hv = gf + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
+                T fp;
+                if constexpr (PK) fp = SF::dec(ghigh ? (gf >> 16) : gf) * finv;
+                else fp = gf;
+                const T hv = fp + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
                 // the iteration pulling it: p = 1, 3 from its own row (k = rel + 3),
                 // p = 5, 6 from the row before (k = rel + 2), p = 7, 8 from the row after
                 const int rel = k - (pi == 0 ? 3 : (pi == 1 ? 2 : 4));
@@ -471,17 +608,16 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
         constexpr int DD = (EDGE && sizeof(T) == 8) ? 1 : D;
         static_assert(L % DD == 0, "prefetch sets must divide the loop trip");
         double UP[DD][2];
-        T FP[DD][9];
+        Raw FP[DD][NRAW];
         T zero9[9];
 #pragma unroll
         for (int q = 0; q < 9; q++) zero9[q] = T(0);
 
         // iteration r, the block's relative row rel (0..HR-1)
-        auto iteration = [&](int r, int rel, double Us[2], T Fs[9]) {
+        auto iteration = [&](int r, int rel, double Us[2], Raw Fs[NRAW]) {
             double U3[2] = {Us[0], Us[1]};
             T F1[9];
-#pragma unroll
-            for (int q = 0; q < 9; q++) F1[q] = Fs[q];
+            decode(Fs, F1);
             load_u(r + 3 + DD, Us);
             load_f(r + 1 + DD, Fs);
             const double ul[2] = {hl.un[0][rel][0], hl.un[0][rel][1]};
@@ -659,7 +795,7 @@ __device__ void node_sigma(const InitLike& a, int gx, int gy, double s[2]) {
 
 // fc'_0 = f_eq(r0 = -rho0 tr H(u0), j0, Pi(H(u0))): an equilibrium is unchanged by
 // the collision without forcing.
-template <typename T>
+template <int PR>
 __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -675,15 +811,15 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const double m2xy = -a.b.mu * (H[1] + H[2]) * ic2;
     const double m2yy = -a.b.mu * (H[3] + H[3] + tr) * ic2;
     const double m1x = a.j0[o] * a.inv_c, m1y = a.j0[plane + o] * a.inv_c;
-    T* f = reinterpret_cast<T*>(a.f);
+    double v[9];
 #pragma unroll
-    for (int q = 0; q < 9; q++)
-        f[q * plane + o] = T(feq_q<double>(q, r0, m1x, m1y, m2xx, m2xy, m2yy));
+    for (int q = 0; q < 9; q++) v[q] = feq_q<double>(q, r0, m1x, m1y, m2xx, m2xy, m2yy);
+    pop_put_all<PR>(a.f, plane, o, v, a.fscale);
 }
 
 // ---- read-out -----------------------------------------------------------------------------
 
-template <typename T, int MAT>
+template <int PR, int MAT>
 __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -692,7 +828,6 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     const size_t plane = (size_t)g.plane;
     const size_t o = (size_t)gy * g.pitch + gx;
     const size_t oc = (size_t)gy * g.nx + gx, pc = (size_t)g.nx * g.ny;  // compact output
-    const T* fs = reinterpret_cast<const T*>(a.f);
     double* d = a.dst;
     switch (a.field) {
     case 0:  // U
@@ -703,7 +838,7 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
         double s[2], mx = 0, my = 0;
         node_sigma<MAT>(a.b, gx, gy, s);
         for (int q = 0; q < 9; q++) {
-            const double v = (double)fs[q * plane + o];
+            const double v = pop_get<PR>(a.f, plane, o, q, a.finv);
             mx += ex(q) * v;
             my += ey(q) * v;
         }
@@ -715,7 +850,7 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     case 3: {  // PI = c^2 M2'
         double r = 0, pxx = 0, pxy = 0, pyy = 0;
         for (int q = 0; q < 9; q++) {
-            const double v = (double)fs[q * plane + o];
+            const double v = pop_get<PR>(a.f, plane, o, q, a.finv);
             r += v;
             pxx += ex(q) * ex(q) * v;
             pxy += ex(q) * ey(q) * v;
@@ -752,7 +887,7 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
 
 // ---- diagnostics: fixed-order block reductions ------------------------------------------------
 
-template <typename T, int MAT>
+template <int PR, int MAT>
 __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
     const Geometry& g = a.b.g;
     const int nbx = (g.nx + 63) / 64;
@@ -762,10 +897,9 @@ __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
     if (gx < g.nx && gy < g.ny) {
         const size_t plane = (size_t)g.plane;
         const size_t o = (size_t)gy * g.pitch + gx;
-        const T* fs = reinterpret_cast<const T*>(a.f);
         double mx = 0, my = 0, s[2];
         for (int q = 0; q < 9; q++) {
-            const double w = (double)fs[q * plane + o];
+            const double w = pop_get<PR>(a.f, plane, o, q, a.finv);
             mx += ex(q) * w;
             my += ey(q) * w;
         }
@@ -828,36 +962,36 @@ static int march_chunk(const Geometry& g, int nstrip, int L) {
     return (int)(m * L - 2);
 }
 
-template <typename T, int MAT, int HR, int D>
+template <int PR, int MAT, int HR, int D>
 static void launch_march(const StepArgs& a, hipStream_t st) {
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);
     const int nstrip = a.g.pitch / 64;
     const int chunk = march_chunk(a.g, nstrip, L);
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
-    hipLaunchKernelGGL((march_kernel<T, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
+    hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
                        nstrip, nchunk, chunk);
 }
 
-template <typename T, int MAT>
-static hipError_t step_m(const StepArgs& a, hipStream_t st) {
+template <int PR>
+static hipError_t step_p(int material, const StepArgs& a, hipStream_t st) {
     // halo blocks of 6 rows, loads of 2 rows in flight: the fastest of the
     // shapes measured on the 8192^2 workload (halo blocks of 2 to 6 rows, 2 or 3
     // rows in flight), in FP32 and FP64
-    launch_march<T, MAT, 6, 2>(a, st);
+    switch (material) {
+    case MAT_SVK: launch_march<PR, MAT_SVK, 6, 2>(a, st); break;
+    case MAT_NH: launch_march<PR, MAT_NH, 6, 2>(a, st); break;
+    default: launch_march<PR, MAT_LIN, 6, 2>(a, st); break;
+    }
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t step_t(int material, const StepArgs& a, hipStream_t st) {
-    switch (material) {
-    case MAT_SVK: return step_m<T, MAT_SVK>(a, st);
-    case MAT_NH: return step_m<T, MAT_NH>(a, st);
-    default: return step_m<T, MAT_LIN>(a, st);
+hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: return step_p<PREC_F64>(material, a, st);
+    case PREC_F32: return step_p<PREC_F32>(material, a, st);
+    case PREC_F16: return step_p<PREC_F16>(material, a, st);
+    default: return step_p<PREC_BF16>(material, a, st);
     }
-}
-
-hipError_t launch_step(int f64, int material, const StepArgs& a, hipStream_t st) {
-    return f64 ? step_t<double>(material, a, st) : step_t<float>(material, a, st);
 }
 
 // ---- plain copy: the reference kernel for hardware byte counters -------------------------------
@@ -885,44 +1019,58 @@ hipError_t launch_copy(void* dst, const void* src, size_t n4, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_init(int f64, const InitArgs& a, hipStream_t st) {
+hipError_t launch_init(int prec, const InitArgs& a, hipStream_t st) {
     const dim3 grid((a.b.g.nx + 63) / 64, (a.b.g.ny + 3) / 4), block(256);
-    if (f64) hipLaunchKernelGGL((init_kernel<double>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((init_kernel<float>), grid, block, 0, st, a);
-    return hipGetLastError();
-}
-
-template <typename T>
-static hipError_t read_t(int material, const ReadArgs& a, hipStream_t st) {
-    const dim3 grid((a.b.g.nx + 63) / 64, (a.b.g.ny + 3) / 4), block(256);
-    switch (material) {
-    case MAT_SVK: hipLaunchKernelGGL((read_kernel<T, MAT_SVK>), grid, block, 0, st, a); break;
-    case MAT_NH: hipLaunchKernelGGL((read_kernel<T, MAT_NH>), grid, block, 0, st, a); break;
-    default: hipLaunchKernelGGL((read_kernel<T, MAT_LIN>), grid, block, 0, st, a); break;
+    switch (prec) {
+    case PREC_F64: hipLaunchKernelGGL((init_kernel<PREC_F64>), grid, block, 0, st, a); break;
+    case PREC_F32: hipLaunchKernelGGL((init_kernel<PREC_F32>), grid, block, 0, st, a); break;
+    case PREC_F16: hipLaunchKernelGGL((init_kernel<PREC_F16>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((init_kernel<PREC_BF16>), grid, block, 0, st, a); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_read(int f64, int material, const ReadArgs& a, hipStream_t st) {
-    return f64 ? read_t<double>(material, a, st) : read_t<float>(material, a, st);
+template <int PR>
+static hipError_t read_p(int material, const ReadArgs& a, hipStream_t st) {
+    const dim3 grid((a.b.g.nx + 63) / 64, (a.b.g.ny + 3) / 4), block(256);
+    switch (material) {
+    case MAT_SVK: hipLaunchKernelGGL((read_kernel<PR, MAT_SVK>), grid, block, 0, st, a); break;
+    case MAT_NH: hipLaunchKernelGGL((read_kernel<PR, MAT_NH>), grid, block, 0, st, a); break;
+    default: hipLaunchKernelGGL((read_kernel<PR, MAT_LIN>), grid, block, 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_read(int prec, int material, const ReadArgs& a, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: return read_p<PREC_F64>(material, a, st);
+    case PREC_F32: return read_p<PREC_F32>(material, a, st);
+    case PREC_F16: return read_p<PREC_F16>(material, a, st);
+    default: return read_p<PREC_BF16>(material, a, st);
+    }
 }
 
 int diag_blocks(const Geometry& g) { return ((g.nx + 63) / 64) * ((g.ny + 3) / 4); }
 
-template <typename T>
-static hipError_t diag_t(int material, const ReadArgs& a, double* out, hipStream_t st) {
+template <int PR>
+static hipError_t diag_p(int material, const ReadArgs& a, double* out, hipStream_t st) {
     const int nblk = diag_blocks(a.b.g);
     switch (material) {
-    case MAT_SVK: hipLaunchKernelGGL((diag_kernel<T, MAT_SVK>), dim3(nblk), dim3(256), 0, st, a); break;
-    case MAT_NH: hipLaunchKernelGGL((diag_kernel<T, MAT_NH>), dim3(nblk), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((diag_kernel<T, MAT_LIN>), dim3(nblk), dim3(256), 0, st, a); break;
+    case MAT_SVK: hipLaunchKernelGGL((diag_kernel<PR, MAT_SVK>), dim3(nblk), dim3(256), 0, st, a); break;
+    case MAT_NH: hipLaunchKernelGGL((diag_kernel<PR, MAT_NH>), dim3(nblk), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((diag_kernel<PR, MAT_LIN>), dim3(nblk), dim3(256), 0, st, a); break;
     }
     hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(256), 0, st, a.partial, nblk, out);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int f64, int material, const ReadArgs& a, double* out, hipStream_t st) {
-    return f64 ? diag_t<double>(material, a, out, st) : diag_t<float>(material, a, out, st);
+hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: return diag_p<PREC_F64>(material, a, out, st);
+    case PREC_F32: return diag_p<PREC_F32>(material, a, out, st);
+    case PREC_F16: return diag_p<PREC_F16>(material, a, out, st);
+    default: return diag_p<PREC_BF16>(material, a, out, st);
+    }
 }
 
 }  // namespace mclbm

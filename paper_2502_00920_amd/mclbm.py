@@ -26,7 +26,7 @@ _lib = C.CDLL(LIB_PATH)
 # ---- enums (include/mclbm.h) ---------------------------------------------------------
 MCLBM_OK, MCLBM_EINVAL, MCLBM_ETOOSMALL, MCLBM_EHIP, MCLBM_EUNSTABLE, MCLBM_ESTATE = 0, -1, -2, -3, -4, -5
 MATERIAL = {"svk": 0, "neohooke": 1, "linear": 2}
-PRECISION = {"f64": 0, "f32": 1}
+PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 SIDE = {"left": 0, "right": 1, "bottom": 2, "top": 3}
 BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
 LOAD = {"zero": 0, "const": 1, "disp_ramp": 2, "linear_ramp": 3, "sin2_ramp": 4,

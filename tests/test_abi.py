@@ -67,6 +67,13 @@ def test_arena_scales_with_precision(M):
     assert b64 >= 2 * 9 * 700 * pitch * 8 + 2 * 2 * 700 * pitch * 8
     assert b32 >= 2 * 9 * 700 * pitch * 4 + 2 * 2 * 700 * pitch * 8
     assert b32 < b64
+    b16, _ = M.mclbm_plan(M.make_params(1000, 700, mu=0.05, nu=0.3, tau=0.55, precision="f16"))
+    bb16, _ = M.mclbm_plan(M.make_params(1000, 700, mu=0.05, nu=0.3, tau=0.55, precision="bf16"))
+    assert b16 == bb16 and b16 >= 2 * 18 * 700 * pitch + 2 * 2 * 700 * pitch * 8 and b16 < b32
+    with pytest.raises(M.MclbmError):
+        p = M.make_params(100, 100, mu=0.05, nu=0.3, tau=0.55)
+        p.precision = 4
+        M.mclbm_plan(p)
 
 
 def test_host_side_errors_without_gpu(M):

@@ -208,6 +208,92 @@ def test_tension8192_full_size(M, precision):
     del o, s
 
 
+# ---- 16-bit population storage: error against the oracle, reported ------------------------
+#
+# No accuracy bound is claimed for FP16 / BF16 storage; the bounds below are
+# regression bounds a few times above the largest errors measured on MI355X
+# (the 32 x 32 tension case at step 1000: FP16 u 3.5e-4, P 2.3e-3; BF16 u 8.6e-3,
+# P 5.1e-2).
+
+HALF_U = {"f16": 1.5e-3, "bf16": 3e-2}
+HALF_P = {"f16": 1e-2, "bf16": 1.5e-1}
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+@pytest.mark.parametrize("nx,ny,code,material", [CASES[0], CASES[1], CASES[5], CASES[7]])
+def test_half_storage_random_state(M, nx, ny, code, material, precision):
+    print_case(f"half storage random-state {nx}x{ny} {code} {material} {precision}")
+    u0 = W.smooth_field(nx, ny, 0.05, seed=nx + ny)
+    j0 = W.random_field(nx, ny, 1e-3, seed=nx * ny)
+    o, s = pair(M, nx, ny, walls(code), material=material, nu=0.2, precision=precision, u0=u0, j0=j0)
+    for n in (1, 30):
+        o.step(n - o.n)
+        s.step(n - s.n)
+        e = compare(o, s, ("u", "p", "j"))
+        print(n, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+        assert e["u"] <= HALF_U[precision] and e["p"] <= HALF_P[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+@pytest.mark.parametrize("name", ["tension32", "shear128", "beam2048"])
+def test_half_storage_workloads(M, name, precision):
+    print_case(f"half storage {name} {precision}")
+    w = {"tension32": W.tension32, "shear128": lambda: W.shear128(0.25), "beam2048": W.beam2048}[name]()
+    stops = {"tension32": [100, 1000], "shear128": [200, 1000], "beam2048": [50, 150]}[name]
+    for n, e, umax in run_workload(M, w, precision, stops):
+        assert np.isfinite(umax)
+        assert e["u"] <= HALF_U[precision] and e["p"] <= HALF_P[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+def test_half_storage_full_size(M, precision):
+    """The 8192 x 8192 benchmark lattice in 16-bit storage, every node after 1
+    and 3 steps from a generic seeded state."""
+    print_case(f"tension8192 full size {precision}")
+    w = W.tension_large(8192, 1000)
+    n = w.nx
+    u0 = W.smooth_field(n, n, 0.02, seed=11) + W.random_field(n, n, 1e-4, seed=12)
+    j0 = W.random_field(n, n, 1e-3, seed=13)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    o, s = pair(M, n, n, {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()},
+                material=w.material, mu=w.mu, nu=w.nu, tau=w.tau, precision=precision, u0=u0, j0=j0,
+                threads=max(1, min(16, cores)))
+    del u0, j0
+    for k in (1, 3):
+        o.step(k - o.n)
+        s.step(k - s.n)
+        e = compare(o, s, ("u", "p"))
+        print(k, {f: f"{v:.2e}" for f, v in e.items()}, flush=True)
+        assert e["u"] <= HALF_U[precision] and e["p"] <= HALF_P[precision], (k, e)
+    del o, s
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+def test_half_storage_determinism_and_rest(M, precision):
+    print_case(f"half storage determinism, checkpoint, rest {precision}")
+    w = W.shear128(0.25)
+    runs = []
+    for _ in range(2):
+        s = M.sim_from_workload(w, precision)
+        s.init(W.smooth_field(w.nx, w.ny, 0.02, seed=1))
+        s.step(200)
+        runs.append(s.read("u"))
+    assert np.array_equal(runs[0], runs[1])
+    s = M.sim_from_workload(w, precision)
+    s.init(W.smooth_field(w.nx, w.ny, 0.02, seed=1))
+    s.step(80)
+    buf = s.save()
+    t = M.sim_from_workload(w, precision)
+    t.load(buf)
+    t.step(120)
+    assert np.array_equal(t.read("u"), runs[0])
+    r = M.Sim(300, 200, mu=0.05, nu=0.3, tau=0.55, material="neohooke", precision=precision)
+    r.init()
+    r.step(20)
+    for f in ("u", "j", "r", "pi", "p"):
+        assert np.all(r.read(f) == 0.0)
+
+
 # ---- properties at size ----------------------------------------------------------------------
 
 def test_rest_state_bitwise(M):
