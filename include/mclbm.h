@@ -56,12 +56,15 @@ enum mclbm_material { MCLBM_SVK = 0, MCLBM_NEOHOOKE = 1, MCLBM_LINEAR = 2 };
  * u is stored and integrated in FP64 in every mode, and its differences (the
  * displacement gradient) are taken in FP64.
  *   F64   populations FP64, arithmetic FP64 (the plain method)
- *   F32   populations FP32, stresses, source, collision and wall rules in FP32
- *   F16   populations stored as FP16, arithmetic FP32.  The rest state of the
+ *   F32   populations stored in FP32; stresses, source, pulls and wall rules in
+ *         FP32; the moments, the equilibrium and the BGK relaxation in FP64
+ *         (the D2Q9 weights are inexact in FP32, and an FP32 equilibrium
+ *         would scale j and Pi by about 1 + 1e-8 in every collision)
+ *   F16   populations stored as FP16, arithmetic as F32.  The rest state of the
  *         scheme has f = 0, so the stored values are the deviations from that
  *         equilibrium; they are kept times 2^(12 - floor(log2 rho0)), which
  *         holds |f| from about 1.5e-8 rho0 to 16 rho0 in FP16's normal range
- *   BF16  populations stored as BF16 (unscaled), arithmetic FP32
+ *   BF16  populations stored as BF16 (unscaled), arithmetic as F32
  * The two 16-bit modes keep 18 bytes per node and buffer instead of 36 (F32)
  * or 72 (F64).  Their error against F64 is reported per workload; no bound is
  * claimed. */

@@ -93,12 +93,16 @@ __device__ __forceinline__ float bf16_value(uint32_t b) { return __builtin_bit_c
 
 template <int PR>
 struct Store {  // PREC_F64, PREC_F32: plain planes
-    using T = typename std::conditional<PR == PREC_F64, double, float>::type;
+    using T = typename std::conditional<PR == PREC_F64, double, float>::type;  // arithmetic
+    using TS = T;  // stresses, source and their halo
+    using ST = T;  // storage
     static constexpr bool packed = false;
 };
 template <>
 struct Store<PREC_F16> {
     using T = float;
+    using TS = float;
+    using ST = uint16_t;
     static constexpr bool packed = true;
     __device__ static uint32_t enc(float v) { return f16_bits(v); }
     __device__ static float dec(uint32_t b) { return f16_value(b); }
@@ -106,6 +110,8 @@ struct Store<PREC_F16> {
 template <>
 struct Store<PREC_BF16> {
     using T = float;
+    using TS = float;
+    using ST = uint16_t;
     static constexpr bool packed = true;
     __device__ static uint32_t enc(float v) { return bf16_bits(v); }
     __device__ static float dec(uint32_t b) { return bf16_value(b); }
@@ -116,7 +122,7 @@ template <int PR>
 __device__ __forceinline__ double pop_get(const void* f, size_t plane, size_t o, int q, double finv) {
     using S = Store<PR>;
     if constexpr (!S::packed) {
-        return (double)reinterpret_cast<const typename S::T*>(f)[(size_t)q * plane + o];
+        return (double)reinterpret_cast<const typename S::ST*>(f)[(size_t)q * plane + o];
     } else {
         const uint32_t* w = reinterpret_cast<const uint32_t*>(f);
         if (q == 8) return (double)S::dec(reinterpret_cast<const uint16_t*>(w + 4 * plane)[o]) * finv;
@@ -128,7 +134,7 @@ template <int PR>
 __device__ __forceinline__ void pop_put_all(void* f, size_t plane, size_t o, const double v[9], double fscale) {
     using S = Store<PR>;
     if constexpr (!S::packed) {
-        for (int q = 0; q < 9; q++) reinterpret_cast<typename S::T*>(f)[(size_t)q * plane + o] = (typename S::T)v[q];
+        for (int q = 0; q < 9; q++) reinterpret_cast<typename S::ST*>(f)[(size_t)q * plane + o] = (typename S::ST)v[q];
     } else {
         uint32_t* w = reinterpret_cast<uint32_t*>(f);
         for (int k = 0; k < 4; k++)
@@ -189,15 +195,15 @@ __device__ __forceinline__ V from_next(V v, V edge) { return dpp_shift<kDppWaveS
 // wrapped) data and store into the row padding; rows that prime the pipeline
 // store into row ny.
 
-template <typename T, int HR>
+template <typename T, typename TS, int HR>
 struct Halo {  // rows k = 0..HR+5 of a block are rows r0 - 3 + k
     static constexpr int HK = HR + 6;
     double u[2][HK][5][2];  // [side][k][column c][comp]; side 0: x0-3+c, side 1: x0+62+c
-    T t[2][HK][3][4];       // T at c = 1, 2, 3
-    T s[2][HK][2];          // sigma at c = 2
+    TS t[2][HK][3][4];      // T at c = 1, 2, 3
+    TS s[2][HK][2];         // sigma at c = 2
     // what iteration rel of the block reads, side by side
     double un[2][HR][2];    // u at c = 2, row r0 + rel + 2
-    T tn[2][HR][4];         // T at c = 2, row r0 + rel + 1
+    TS tn[2][HR][4];        // T at c = 2, row r0 + rel + 1
     T hn[2][HR][4];         // pull sources at c = 2: side 0 p = 1, 5, 8 from rows
                             // r0+rel, r0+rel-1, r0+rel+1; side 1 p = 3, 6, 7 likewise
 };
@@ -225,21 +231,23 @@ struct Flag {
 template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
     using SF = Store<PR>;
-    using T = typename SF::T;  // arithmetic type
+    using T = typename SF::T;    // arithmetic type
+    using TS = typename SF::TS;  // of the stresses and the source
     constexpr bool PK = SF::packed;
     // a row of one lane's populations as loaded: nine values, or five packed words
-    using Raw = typename std::conditional<PK, uint32_t, T>::type;
+    using ST = typename SF::ST;
+    using Raw = typename std::conditional<PK, uint32_t, ST>::type;
     constexpr int NRAW = PK ? 5 : 9;
     constexpr int HK = HR + 6;
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);  // iterations per loop trip
     constexpr int NU = 5 * HK, NT = 3 * (HK - 2), NS = HK - 4;         // halo items per side
     static_assert(2 * NU <= 128 && NU <= 64 && 2 * NT <= 64 && 6 * NS <= 64 && HR >= 1 && D >= 1,
                   "halo block too long for one wave");
-    __shared__ Halo<T, HR> halo_lds[4];
+    __shared__ Halo<T, TS, HR> halo_lds[4];
     const Geometry g = a.g;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    Halo<T, HR>& hl = halo_lds[wv];
+    Halo<T, TS, HR>& hl = halo_lds[wv];
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
     if (item >= nstrip * nchunk) return;
     const int strip = item % nstrip, chk = item / nstrip;
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
     const uint32_t pbD = (uint32_t)(plane * sizeof(double));
     // bytes per plane: of T (three planes per resource), or of 32-bit words (four
     // planes in one resource, the 16-bit plane in another)
-    const uint32_t pbT = (uint32_t)(plane * (PK ? 4 : sizeof(T)));
+    const uint32_t pbT = (uint32_t)(plane * (PK ? 4 : sizeof(ST)));
     const char* fs = reinterpret_cast<const char*>(a.fsrc);
     char* fd = reinterpret_cast<char*>(a.fdst);
     const __amdgpu_buffer_rsrc_t rs0 = rsrc(fs, (PK ? 4 : 3) * pbT),
@@ -268,9 +276,9 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
     const __amdgpu_buffer_rsrc_t rus = rsrc(a.usrc, 2 * pbD), rud = rsrc(a.udst, 2 * pbD);
     const T finv = T(a.k.finv), fscl = T(a.k.fscale);
     const double idx = a.k.inv_dx;
-    const T ic2 = T(a.k.inv_c2), sbx = T(a.k.sig_b[0]), sby = T(a.k.sig_b[1]);
-    const T lam = T(a.k.lam), mu = T(a.k.mu);
-    const T om = T(a.k.omega);
+    const TS ic2 = TS(a.k.inv_c2), sbx = TS(a.k.sig_b[0]), sby = TS(a.k.sig_b[1]);
+    const TS lam = TS(a.k.lam), mu = TS(a.k.mu);
+    const double omd = a.k.omega;
     const uint32_t trash = (uint32_t)(g.ny * g.pitch + vx);  // row ny: written, never read
 
     auto run = [&](auto edge_flag) {
@@ -306,10 +314,10 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                     f[w] = __builtin_amdgcn_raw_buffer_load_b32(rs0, o * 4u, (uint32_t)w * pbT, 0);
                 f[4] = __builtin_amdgcn_raw_buffer_load_b16(rs1, o * 2u, 0u, 0);
             } else {
-                const uint32_t ob = o * (uint32_t)sizeof(T);
+                const uint32_t ob = o * (uint32_t)sizeof(ST);
 #pragma unroll
                 for (int q = 0; q < 9; q++)
-                    f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, T(0));
+                    f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, ST(0));
             }
         };
         auto decode = [&](const Raw f[NRAW], T F[9]) {
@@ -322,7 +330,7 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 F[8] = SF::dec(f[4]) * finv;
             } else {
 #pragma unroll
-                for (int q = 0; q < 9; q++) F[q] = f[q];
+                for (int q = 0; q < 9; q++) F[q] = T(f[q]);
             }
         };
         auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
@@ -338,16 +346,16 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 __builtin_amdgcn_raw_buffer_store_b16((unsigned short)SF::enc(fn[8] * fscl), rd1, node * 2u, 0u,
                                                       kCpolNT);
             } else {
-                const uint32_t of = node * (uint32_t)sizeof(T);
+                const uint32_t of = node * (uint32_t)sizeof(ST);
 #pragma unroll
                 for (int q = 0; q < 9; q++)
-                    bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, fn[q]);
+                    bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, ST(fn[q]));
             }
         };
 
         // T = P(H) + Pi(H) at row r of this lane; ul / ur: u of the columns left of
         // lane 0 and right of lane 63
-        auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], T t[4],
+        auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], TS t[4],
                           const double ul[2], const double ur[2]) {
             double lx = from_prev(u0[0], ul[0]), rx = from_next(u0[0], ur[0]);
             double ly = from_prev(u0[1], ul[1]), ry = from_next(u0[1], ur[1]);
@@ -366,29 +374,29 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 dy = hi ? u0[1] : dy;
                 fy = (lo || hi) ? idx : fy;
             }
-            excess_stress<T, MAT>(T((rx - lx) * fx), T((dx - cx) * fy), T((ry - ly) * fx), T((dy - cy) * fy),
-                                  lam, mu, t);
+            excess_stress<TS, MAT>(TS((rx - lx) * fx), TS((dx - cx) * fy), TS((ry - ly) * fx),
+                                   TS((dy - cy) * fy), lam, mu, t);
         };
         // sigma = dt S / c at row r of this lane; tl / tr: T of the columns left of
         // lane 0 and right of lane 63
-        auto sigma = [&](int r, const T tm[4], const T t0[4], const T tp[4], T sg[2], const T tl[4],
-                         const T tr[4]) {
-            T lxx = from_prev(t0[0], tl[0]), rxx = from_next(t0[0], tr[0]);
-            T lyx = from_prev(t0[2], tl[2]), ryx = from_next(t0[2], tr[2]);
-            T fx = T(0.5), fy = T(0.5);
-            T cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3];
+        auto sigma = [&](int r, const TS tm[4], const TS t0[4], const TS tp[4], TS sg[2], const TS tl[4],
+                         const TS tr[4]) {
+            TS lxx = from_prev(t0[0], tl[0]), rxx = from_next(t0[0], tr[0]);
+            TS lyx = from_prev(t0[2], tl[2]), ryx = from_next(t0[2], tr[2]);
+            TS fx = TS(0.5), fy = TS(0.5);
+            TS cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3];
             if constexpr (EDGE) {
                 lxx = atL ? t0[0] : lxx;
                 lyx = atL ? t0[2] : lyx;
                 rxx = atR ? t0[0] : rxx;
                 ryx = atR ? t0[2] : ryx;
-                fx = (atL || atR) ? T(1) : fx;
+                fx = (atL || atR) ? TS(1) : fx;
                 const bool lo = lo_row(r), hi = hi_row(r);
                 cxy = lo ? t0[1] : cxy;
                 cyy = lo ? t0[3] : cyy;
                 dxy = hi ? t0[1] : dxy;
                 dyy = hi ? t0[3] : dyy;
-                fy = (lo || hi) ? T(1) : fy;
+                fy = (lo || hi) ? TS(1) : fy;
             }
             sg[0] = ic2 * ((rxx - lxx) * fx + (dxy - cxy) * fy) + sbx;
             sg[1] = ic2 * ((ryx - lyx) * fx + (dyy - cyy) * fy) + sby;
@@ -427,7 +435,7 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 const uint32_t* w = reinterpret_cast<const uint32_t*>(fs);
                 gf = p == 8 ? w[4 * plane + (o >> 1)] : w[(size_t)(p >> 1) * plane + o];
             } else {
-                gf = reinterpret_cast<const T*>(fs)[(size_t)p * plane + o];
+                gf = reinterpret_cast<const ST*>(fs)[(size_t)p * plane + o];
             }
         };
         auto halo = [&](int r0) {
@@ -459,9 +467,9 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 const double cx = lo ? u0x : hl.u[sd][k - 1][c][0], dx = hi ? u0x : hl.u[sd][k + 1][c][0];
                 const double cy = lo ? u0y : hl.u[sd][k - 1][c][1], dy = hi ? u0y : hl.u[sd][k + 1][c][1];
                 const double fy = (lo || hi) ? idx : 0.5 * idx;
-                T t[4];
-                excess_stress<T, MAT>(T((bx - ax) * fx), T((dx - cx) * fy), T((by - ay) * fx),
-                                      T((dy - cy) * fy), lam, mu, t);
+                TS t[4];
+                excess_stress<TS, MAT>(TS((bx - ax) * fx), TS((dx - cx) * fy), TS((by - ay) * fx),
+                                       TS((dy - cy) * fy), lam, mu, t);
 #pragma unroll
                 for (int q = 0; q < 4; q++) hl.t[sd][k][c - 1][q] = t[q];
                 // T at c = 2 for the iteration that needs it: row r0 + rel + 1, k = rel + 4
@@ -476,16 +484,16 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 const int X = colp(sd == 0 ? x0 - 1 : x0 + 64);
                 const int r = r0 - 3 + k;
                 const bool aL = EDGE && !g.px && X == 0, aR = EDGE && !g.px && X == g.nx - 1;
-                const T t0xx = hl.t[sd][k][1][0], t0yx = hl.t[sd][k][1][2];
-                const T axx = aL ? t0xx : hl.t[sd][k][0][0], bxx = aR ? t0xx : hl.t[sd][k][2][0];
-                const T ayx = aL ? t0yx : hl.t[sd][k][0][2], byx = aR ? t0yx : hl.t[sd][k][2][2];
-                const T fx = (aL || aR) ? T(1) : T(0.5);
+                const TS t0xx = hl.t[sd][k][1][0], t0yx = hl.t[sd][k][1][2];
+                const TS axx = aL ? t0xx : hl.t[sd][k][0][0], bxx = aR ? t0xx : hl.t[sd][k][2][0];
+                const TS ayx = aL ? t0yx : hl.t[sd][k][0][2], byx = aR ? t0yx : hl.t[sd][k][2][2];
+                const TS fx = (aL || aR) ? TS(1) : TS(0.5);
                 const bool lo = lo_row(r), hi = hi_row(r);
-                const T cxy = lo ? hl.t[sd][k][1][1] : hl.t[sd][k - 1][1][1];
-                const T dxy = hi ? hl.t[sd][k][1][1] : hl.t[sd][k + 1][1][1];
-                const T cyy = lo ? hl.t[sd][k][1][3] : hl.t[sd][k - 1][1][3];
-                const T dyy = hi ? hl.t[sd][k][1][3] : hl.t[sd][k + 1][1][3];
-                const T fy = (lo || hi) ? T(1) : T(0.5);
+                const TS cxy = lo ? hl.t[sd][k][1][1] : hl.t[sd][k - 1][1][1];
+                const TS dxy = hi ? hl.t[sd][k][1][1] : hl.t[sd][k + 1][1][1];
+                const TS cyy = lo ? hl.t[sd][k][1][3] : hl.t[sd][k - 1][1][3];
+                const TS dyy = hi ? hl.t[sd][k][1][3] : hl.t[sd][k + 1][1][3];
+                const TS fy = (lo || hi) ? TS(1) : TS(0.5);
                 hl.s[sd][k][0] = ic2 * ((bxx - axx) * fx + (dxy - cxy) * fy) + sbx;
                 hl.s[sd][k][1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
             }
@@ -495,8 +503,8 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 const int p = halo_pop(sd, pi);
                 T fp;
                 if constexpr (PK) fp = SF::dec(ghigh ? (gf >> 16) : gf) * finv;
-                else fp = gf;
-                const T hv = fp + T(3) * wq<T>(p) * (T(ex(p)) * hl.s[sd][k][0] + T(ey(p)) * hl.s[sd][k][1]);
+                else fp = T(gf);
+                const T hv = fp + T(3) * wq<T>(p) * T(TS(ex(p)) * hl.s[sd][k][0] + TS(ey(p)) * hl.s[sd][k][1]);
                 // the iteration pulling it: p = 1, 3 from its own row (k = rel + 3),
                 // p = 5, 6 from the row before (k = rel + 2), p = 7, 8 from the row after
                 const int rel = k - (pi == 0 ? 3 : (pi == 1 ? 2 : 4));
@@ -540,7 +548,9 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
         };
         // links crossing only the x wall of this lane: p = (sx, 0), (sx, 1), (sx, -1),
         // sx = -(outward normal); the outgoing link reflected is q = (-sx, -ey)
-        auto xwall_links = [&](const T fo[9], const T g0[2], const T t0[4], T f[9]) {
+        auto xwall_links = [&](const T fo[9], const TS g0s[2], const TS t0s[4], T f[9]) {
+            const T g0[2] = {T(g0s[0]), T(g0s[1])};
+            const T t0[4] = {T(t0s[0]), T(t0s[1]), T(t0s[2]), T(t0s[3])};
             T r0, mxx, myy;
             r0_m2(fo, r0, mxx, myy);
             const T Mxx = kxx + t0[0] * c2i;
@@ -567,7 +577,9 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
         };
         // links crossing the y wall of row 0 (onB) or ny-1, with the corner rules for
         // those that cross an x wall too (wave-uniform: two rows per lattice)
-        auto ywall_links = [&](bool onB, const T fo[9], const T g0[2], const T t0[4], T f[9]) {
+        auto ywall_links = [&](bool onB, const T fo[9], const TS g0s[2], const TS t0s[4], T f[9]) {
+            const T g0[2] = {T(g0s[0]), T(g0s[1])};
+            const T t0[4] = {T(t0s[0]), T(t0s[1]), T(t0s[2]), T(t0s[3])};
             T r0, mxx, myy;
             r0_m2(fo, r0, mxx, myy);
             const T syw = onB ? T(-1) : T(1);
@@ -600,8 +612,8 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
 
         // ---- the row pipeline
         double U0[2], U1[2], U2[2], tmp[2];
-        T T0[4], T1[4];
-        T Gm[2] = {T(0), T(0)}, G0[2] = {T(0), T(0)};
+        TS T0[4], T1[4];
+        TS Gm[2] = {TS(0), TS(0)}, G0[2] = {TS(0), TS(0)};
         T Fm[9], F0[9];
         // rows of loads in flight: the FP64 edge path keeps one, which leaves the
         // registers its wall rules need (its waves are a few percent of the grid)
@@ -622,9 +634,9 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
             load_f(r + 1 + DD, Fs);
             const double ul[2] = {hl.un[0][rel][0], hl.un[0][rel][1]};
             const double ur[2] = {hl.un[1][rel][0], hl.un[1][rel][1]};
-            T T2[4], G1[2];
+            TS T2[4], G1[2];
             stress(r + 2, U1, U2, U3, T2, ul, ur);
-            T tl[4], tr[4];
+            TS tl[4], tr[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 tl[q] = hl.tn[0][rel][q];
@@ -634,14 +646,14 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
 
             T h[9];
             h[0] = F0[0];
-            h[1] = F0[1] + T(3) * wq<T>(1) * G0[0];
-            h[3] = F0[3] - T(3) * wq<T>(3) * G0[0];
-            h[2] = Fm[2] + T(3) * wq<T>(2) * Gm[1];
-            h[5] = Fm[5] + T(3) * wq<T>(5) * (Gm[0] + Gm[1]);
-            h[6] = Fm[6] + T(3) * wq<T>(6) * (Gm[1] - Gm[0]);
-            h[4] = F1[4] - T(3) * wq<T>(4) * G1[1];
-            h[7] = F1[7] - T(3) * wq<T>(7) * (G1[0] + G1[1]);
-            h[8] = F1[8] + T(3) * wq<T>(8) * (G1[0] - G1[1]);
+            h[1] = F0[1] + T(3) * wq<T>(1) * T(G0[0]);
+            h[3] = F0[3] - T(3) * wq<T>(3) * T(G0[0]);
+            h[2] = Fm[2] + T(3) * wq<T>(2) * T(Gm[1]);
+            h[5] = Fm[5] + T(3) * wq<T>(5) * T(Gm[0] + Gm[1]);
+            h[6] = Fm[6] + T(3) * wq<T>(6) * T(Gm[1] - Gm[0]);
+            h[4] = F1[4] - T(3) * wq<T>(4) * T(G1[1]);
+            h[7] = F1[7] - T(3) * wq<T>(7) * T(G1[0] + G1[1]);
+            h[8] = F1[8] + T(3) * wq<T>(8) * T(G1[0] - G1[1]);
             T hL[4], hR[4];
 #pragma unroll
             for (int q = 0; q < 4; q++) {
@@ -663,28 +675,33 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
                 if (!g.py && (r == 0 || r == g.ny - 1)) ywall_links(r == 0, F0, G0, T0, f);
             }
 
-            T rho = T(0), m1x = T(0), m1y = T(0), m2xx = T(0), m2xy = T(0), m2yy = T(0);
-            T o1x = T(0), o1y = T(0);
+            // Moments, equilibrium and relaxation in FP64 in every mode: the D2Q9
+            // weights are not exact in FP32 (3 (2 w1 + 4 w5) rounds to 1 + 7.5e-9),
+            // so an FP32 equilibrium scales j and Pi by about 1 + omega 7.5e-9 in
+            // every collision, a bias that compounds over the steps.
+            double rho = 0, m1x = 0, m1y = 0, m2xx = 0, m2xy = 0, m2yy = 0;
+            double o1x = 0, o1y = 0;
 #pragma unroll
             for (int q = 0; q < 9; q++) {
-                rho += f[q];
-                if (ex(q)) m1x += T(ex(q)) * f[q];
-                if (ey(q)) m1y += T(ey(q)) * f[q];
-                if (ex(q)) m2xx += f[q];
-                if (ex(q) * ey(q)) m2xy += T(ex(q) * ey(q)) * f[q];
-                if (ey(q)) m2yy += f[q];
-                if (ex(q)) o1x += T(ex(q)) * F0[q];
-                if (ey(q)) o1y += T(ey(q)) * F0[q];
+                const double fq = (double)f[q], gq = (double)F0[q];
+                rho += fq;
+                if (ex(q)) m1x += ex(q) * fq;
+                if (ey(q)) m1y += ey(q) * fq;
+                if (ex(q)) m2xx += fq;
+                if (ex(q) * ey(q)) m2xy += (ex(q) * ey(q)) * fq;
+                if (ey(q)) m2yy += fq;
+                if (ex(q)) o1x += ex(q) * gq;
+                if (ey(q)) o1y += ey(q) * gq;
             }
             const uint32_t node = (r >= yc && r < ye) ? (uint32_t)(r * g.pitch + vx) : trash;
             T fn[9];
 #pragma unroll
             for (int q = 0; q < 9; q++) {
-                const T e = feq_q<T>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
-                fn[q] = f[q] + om * (e - f[q]);
+                const double e = feq_q<double>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
+                fn[q] = T((double)f[q] + omd * (e - (double)f[q]));
             }
-            store_node(node, U0[0] + a.k.ucoef * (double)(m1x + o1x + G0[0]),
-                       U0[1] + a.k.ucoef * (double)(m1y + o1y + G0[1]), fn);
+            store_node(node, U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
+                       U0[1] + a.k.ucoef * (m1y + o1y + (double)G0[1]), fn);
 
             U0[0] = U1[0]; U0[1] = U1[1];
             U1[0] = U2[0]; U1[1] = U2[1];

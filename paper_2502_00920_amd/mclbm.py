@@ -207,8 +207,11 @@ class Sim:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            mclbm_destroy(h)
             self._h = None
+            try:
+                mclbm_destroy(h)
+            except TypeError:  # interpreter shutdown: the module's globals are gone
+                pass
 
     @property
     def handle(self) -> int:

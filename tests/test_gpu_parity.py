@@ -185,6 +185,23 @@ def test_tension1024(M, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_tension1024_subrun_all_steps(M, precision):
+    """The 1024 x 1024 subrun of the benchmark workload over all its 1000 steps
+    (the FP32 bar holds at the end: no drift of the conserved moments)."""
+    print_case(f"tension1024 subrun, 1000 steps {precision}")
+    w = W.tension_large(1024, 1000)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    o, s = pair(M, w.nx, w.ny, {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()},
+                material=w.material, mu=w.mu, nu=w.nu, tau=w.tau, precision=precision,
+                threads=max(1, min(16, cores)))
+    o.step(1000)
+    s.step(1000)
+    e = compare(o, s, ("u", "p", "j"))
+    print(1000, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], e
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_tension8192_full_size(M, precision):
     """The benchmark lattice in the launch configuration bench.py times
     (8192 x 8192, SVK, the tension walls), from a generic seeded state: every
