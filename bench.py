@@ -5,12 +5,15 @@ Workload: St. Venant-Kirchhoff uniaxial tension on an 8192 x 8192 D2Q9 lattice
 3.2e-3 dx per step, top and bottom traction-free), synthetic and seeded.
 A step is one launch of march_kernel over every node (walls included); inputs
 are resident in HBM before timing starts.  The headline value is MLUPS with
-FP32 population storage (FP64 displacement); the FP64 mode is reported beside
-it.  The roofline figures are those of march_kernel, timed with HIP events
-around each of its launches in the timed region.  Prints one JSON line.
+FP32 population storage (FP64 displacement); FP64 and the 16-bit storage modes
+(FP16, BF16) are reported beside it, each format's error against the FP64
+oracle on the 1024 x 1024 subrun (from the CPU-baseline leg), and a shortened
+run of the serving workload (batched throughput, p50/p99 latency).  The
+roofline figures are those of march_kernel, timed with HIP events around each
+of its launches in the timed region.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--mode all|f32|f64|f16|bf16]
-                  [--n 8192] [--no-cpu-baseline]
+                  [--n 8192] [--no-cpu-baseline] [--no-serving]
   python bench.py --ingest-counters FETCH_DIR WRITE_DIR   (no GPU: rocprofv3
                   counter files -> profiles/step_kernel_traffic.json)
 """
@@ -178,6 +181,14 @@ def subrun_errors(u_ref, p_ref, n: int = 1024, steps: int = 1000) -> dict:
     return out
 
 
+def serving(n: int = 200, steps=(1000, 4000), baseline: int = 20) -> dict:
+    """A shortened run of the serving workload (the full one:
+    python -m paper_2502_00920_amd.serve): batched FP32 capacity, open-loop
+    p50/p99 latency at 0.8 of it, one-at-a-time FP64 throughput."""
+    from paper_2502_00920_amd import serve
+    return serve.serving_report(n=n, steps=steps, baseline=baseline)
+
+
 def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
     """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE;
     counter values in KiB per dispatch) into HBM bytes per launch of
@@ -230,6 +241,7 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--mode", choices=["all", "f32", "f64", "f16", "bf16"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic file from two rocprofv3 --pmc runs of this script and exit")
     args = ap.parse_args()
@@ -284,6 +296,8 @@ def main():
                    "finite": results[m]["finite"]}
     if agree:
         line["rel_l2_u_vs_f64_same_run"] = agree
+    if not args.no_serving:
+        line["serving"] = serving()
     if not args.no_cpu_baseline:
         line["cpu_baseline"], u_ref, p_ref = cpu_baseline()
         line["subrun_error_vs_fp64_oracle"] = subrun_errors(u_ref, p_ref)

@@ -214,6 +214,75 @@ int mclbm_destroy(mclbm_sim* s);
 /* Message of the last error on the calling thread ("" when none). */
 const char* mclbm_last_error(void);
 
+/* ---- Serving: continuous batching of many simulations on one GPU -------------
+ *
+ * A server advances every admitted simulation in rounds of steps_per_round
+ * steps.  The batch is split into four groups (two per material, balanced by
+ * lattice nodes); each round uploads one table (per step and group: the
+ * simulations' buffers, wall values at their own step index and work items)
+ * and replays, on four streams of the server's own joined to the caller's,
+ * one graph per group of batched step launches captured at the first round: a
+ * fixed grid of waves walks the work items of all simulations of the group,
+ * so requests of different lattice sizes, loads and step counts share every
+ * launch, and the groups' launches run side by side.  A simulation's result does not depend on its company:
+ * it is bitwise the same alone and in any mix.  Against mclbm_step it agrees
+ * to rounding (the batch cuts lattices into longer row chunks).  Between rounds the
+ * server collects finished simulations (copying their displacement to the
+ * caller's buffer) and admits waiting requests in arrival order while a slot
+ * is free and their arena (mclbm_plan bytes) fits in the caller's pool.
+ *
+ * Ownership: the caller owns the device pool (256-byte aligned) and the
+ * stream.  The server keeps the first mclbm_server_plan bytes of the pool for
+ * its tables and allocates arenas from the rest; it allocates a pinned host
+ * staging buffer of the same size, four streams (default priority) and some
+ * events, and no device memory.  Single-threaded use. */
+
+typedef struct {
+    int32_t precision;       /* MCLBM_F32 or MCLBM_F64; every request must match  */
+    int32_t steps_per_round; /* 1..1024                                           */
+    int32_t max_active;      /* simulations in flight, 1..1024                    */
+} mclbm_server_config;
+
+enum mclbm_request_state { MCLBM_REQ_WAITING = 0, MCLBM_REQ_ACTIVE = 1, MCLBM_REQ_DONE = 2 };
+
+typedef struct mclbm_server mclbm_server;
+
+/* Device bytes the server keeps at the start of its pool.  EINVAL for a bad
+ * configuration. */
+int mclbm_server_plan(const mclbm_server_config* cfg, size_t* reserved_bytes);
+
+/* Create a server on the current device over the caller's pool.  EINVAL,
+ * ETOOSMALL (pool below the reserved bytes), EHIP. */
+int mclbm_server_create(const mclbm_server_config* cfg, void* pool, size_t pool_bytes, void* stream,
+                        mclbm_server** out);
+
+/* Queue a request: a lattice (mclbm_params, same precision as the server; SVK
+ * or neo-Hooke), its four sides (mclbm_side_spec, left, right, bottom, top),
+ * an initial displacement u0 [2][ny][nx] FP64 on the host (copied; NULL =
+ * zero) and nsteps >= 1.  At completion u_n is written to u_out [2][ny][nx]
+ * FP64 (host memory that must stay valid until then).  Host only.  EINVAL
+ * for bad arguments, ETOOSMALL if the arena can never fit the pool. */
+int mclbm_server_submit(mclbm_server* sv, const mclbm_params* p, const mclbm_side_spec sides[4],
+                        const double* u0, int64_t nsteps, double* u_out, int64_t* id_out);
+
+/* One scheduling turn: wait for the round in flight, collect the requests it
+ * finished (their ids in done_ids, at most cap of them, count in *ndone),
+ * admit waiting requests, enqueue the next round and return without waiting
+ * for it.  A failed request is reported as done with its status. */
+int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int32_t cap, int32_t* ndone);
+
+/* State (enum mclbm_request_state) and status of a request: MCLBM_OK, or
+ * MCLBM_EUNSTABLE when its final state holds non-finite values, or the error
+ * that stopped it. */
+int mclbm_server_result(mclbm_server* sv, int64_t id, int32_t* state, int32_t* status);
+
+/* Requests waiting, in flight and done so far (any pointer may be NULL). */
+int mclbm_server_counts(mclbm_server* sv, int64_t* waiting, int64_t* active, int64_t* done);
+
+/* Wait for the round in flight and release everything (the pool stays with
+ * the caller). */
+int mclbm_server_destroy(mclbm_server* sv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmclbm.so")
-SOURCES = ["mclbm_kernels.hip", "mclbm_api.cpp"]
+SOURCES = ["mclbm_kernels.hip", "mclbm_api.cpp", "mclbm_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

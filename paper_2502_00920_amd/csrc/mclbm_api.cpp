@@ -399,6 +399,36 @@ MCLBM_EXPORT int mclbm_copy(void* dst, const void* src, size_t nbytes, void* str
     return MCLBM_OK;
 }
 
+// ---- internals for the batching server (mclbm_serve.cpp) -------------------------------------
+
+namespace mclbm {
+
+// the arguments of step n + k of s (the populations and displacement ping-pong
+// by step parity) and its work items
+void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e) {
+    const int c = (s->cur + (int)(k & 1)) & 1;
+    e->a.fsrc = at(s, s->L.off_f[c]);
+    e->a.fdst = at(s, s->L.off_f[1 - c]);
+    e->a.usrc = static_cast<const double*>(at(s, s->L.off_u[c]));
+    e->a.udst = static_cast<double*>(at(s, s->L.off_u[1 - c]));
+    e->a.g = s->g;
+    e->a.k = s->k;
+    e->a.w = walls_at(s, s->n + k);
+    march_shape(s->g, &e->nstrip, &e->nchunk, &e->chunk);
+    e->skip = 0;
+    e->pad_ = 0;
+}
+
+// record k steps taken outside mclbm_step
+void advance(mclbm_sim* s, int64_t k) {
+    s->n += k;
+    s->cur = (s->cur + (int)(k & 1)) & 1;
+}
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+}  // namespace mclbm
+
 MCLBM_EXPORT int64_t mclbm_stepno(const mclbm_sim* s) { return s ? s->n : -1; }
 
 MCLBM_EXPORT int mclbm_field_components(int field) {

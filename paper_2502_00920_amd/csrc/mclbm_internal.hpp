@@ -45,6 +45,45 @@ struct ReadArgs {
     double* partial;   // diagnostics: 8 doubles per block
 };
 
+// One simulation's share of one step of a batch: its step arguments, its work
+// items [item0, item0 + nstrip * nchunk) and whether it sits the step out (it
+// has finished its steps in this round).
+struct BatchEntry {
+    StepArgs a;
+    int nstrip, nchunk, chunk;
+    int item0;
+    int skip;
+    int pad_;
+};
+
+// One step of a batch for one material: the simulations in item order.
+struct BatchStep {
+    int nsims, nitems;
+    int pad_[2];
+    BatchEntry e[1];  // nsims entries (the table is allocated for the batch's maximum)
+};
+inline size_t batch_step_bytes(int max_sims) {
+    return (sizeof(BatchStep) + (size_t)(max_sims - 1) * sizeof(BatchEntry) + 255) / 256 * 256;
+}
+
+// work items of one lattice's step in a batch: 64-column strips times row chunks
+void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk);
+// the step for every simulation of one material in the table at step (device
+// memory, read by the kernel), on a fixed grid: graph-capturable
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st);
+
+}  // namespace mclbm
+
+struct mclbm_sim;
+
+namespace mclbm {
+
+// host side, for the batching server: the batch entry of step n + k of s, the
+// step counter advanced by k steps taken in batches, the thread's error message
+void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e);
+void advance(mclbm_sim* s, int64_t k);
+int set_error(int code, const char* msg);
+
 // prec: PREC_F64 / F32 / F16 / BF16.  One launch: march_kernel over every node,
 // walls included.
 hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st);

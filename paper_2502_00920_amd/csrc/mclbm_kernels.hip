@@ -20,6 +20,7 @@
 // the wall rules to their wall nodes.
 // HBM traffic per node and step: 9 populations read and written, u read and
 // written (FP64): 176 B in FP64, 104 B in FP32 storage.
+#include <algorithm>
 #include <type_traits>
 
 #include "mclbm_internal.hpp"
@@ -226,10 +227,16 @@ struct Flag {
     static constexpr bool value = B;
 };
 
-// PR: population storage; HR: rows per halo block; D: rows of loads in flight
-// (prefetch sets)
+template <int PR, int HR>
+using HaloOf = Halo<typename Store<PR>::T, typename Store<PR>::TS, HR>;
+
+// One work item: rows [chk * chunk, chk * chunk + chunk) of the 64-column strip
+// `strip` of the lattice a describes, by one wave (lane = its lane) with its
+// LDS halo block hl.  PR: population storage; HR: rows per halo block; D: rows
+// of loads in flight (prefetch sets).
 template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+__device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl, int lane, int strip, int chk,
+                                           int chunk) {
     using SF = Store<PR>;
     using T = typename SF::T;    // arithmetic type
     using TS = typename SF::TS;  // of the stresses and the source
@@ -243,14 +250,7 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
     constexpr int NU = 5 * HK, NT = 3 * (HK - 2), NS = HK - 4;         // halo items per side
     static_assert(2 * NU <= 128 && NU <= 64 && 2 * NT <= 64 && 6 * NS <= 64 && HR >= 1 && D >= 1,
                   "halo block too long for one wave");
-    __shared__ Halo<T, TS, HR> halo_lds[4];
     const Geometry g = a.g;
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    Halo<T, TS, HR>& hl = halo_lds[wv];
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
-    if (item >= nstrip * nchunk) return;
-    const int strip = item % nstrip, chk = item / nstrip;
     const int x0 = strip * 64;
     const int vx = x0 + lane;  // this lane's column (< pitch)
     const int yc = chk * chunk, ye = min(yc + chunk, g.ny);
@@ -757,6 +757,43 @@ __global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, i
     else run(Flag<true>{});
 }
 
+// The step of one lattice: one work item per wave.
+template <int PR, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+    __shared__ HaloOf<PR, HR> halo_lds[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
+    if (item >= nstrip * nchunk) return;
+    march_item<PR, MAT, HR, D>(a, halo_lds[wv], lane, item % nstrip, item / nstrip, chunk);
+}
+
+// The step of a batch of lattices of one material: a fixed grid of persistent
+// waves walks the work items of every simulation in the table (which lives in
+// device memory, so that a captured launch serves any batch); block b takes
+// items 4b..4b+3, then the same plus four times the grid, so that neighbouring
+// strips run on one CU and share their halo lines in its L2.  An item's work
+// depends only on its own lattice, so a simulation's results do not depend on
+// its company.
+constexpr int kBatchBlocks = 512;  // two blocks of four waves per CU
+
+template <int PR, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
+    __shared__ HaloOf<PR, HR> halo_lds[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nsims = step->nsims, nitems = step->nitems;
+    int s = 0;  // the simulation of the current item (items are in simulation order)
+    for (int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv); item < nitems;
+         item += gridDim.x * 4) {
+        while (s + 1 < nsims && step->e[s + 1].item0 <= item) s++;
+        const BatchEntry& e = step->e[s];
+        if (e.skip) continue;
+        const int local = item - e.item0;
+        march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
+    }
+}
+
 // ---- per-node helpers for init, read-out and diagnostics (FP64, global loads) ----------
 
 __device__ __forceinline__ double ld_u(const InitLike& a, int c, int gx, int gy) {
@@ -987,6 +1024,30 @@ static void launch_march(const StepArgs& a, hipStream_t st) {
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
     hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
                        nstrip, nchunk, chunk);
+}
+
+// In a batch the other lattices supply the waves: chunks of 34 rows (or the
+// whole height, if less).  A step of a batch lasts about one chunk's march, so
+// shorter chunks end it sooner, at the price of the two rows that prime each
+// chunk; 34 rows gave the highest throughput on the serving mix (64: -9 %,
+// 22: even, 10: -9 %).
+void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
+    *nstrip = g.pitch / 64;
+    const int m = std::min(6, (g.ny + 2 + 5) / 6);
+    *chunk = 6 * m - 2;
+    *nchunk = (g.ny + *chunk - 1) / *chunk;
+}
+
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st) {
+    const dim3 grid(kBatchBlocks), block(256);
+    if (prec == PREC_F64) {
+        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        else hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_NH, 6, 2>), grid, block, 0, st, step);
+    } else {
+        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        else hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_NH, 6, 2>), grid, block, 0, st, step);
+    }
+    return hipGetLastError();
 }
 
 template <int PR>

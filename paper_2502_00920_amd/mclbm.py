@@ -46,6 +46,10 @@ class mclbm_side_spec(C.Structure):
                 ("t0", C.c_double), ("t1", C.c_double), ("width", C.c_double)]
 
 
+class mclbm_server_config(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("steps_per_round", C.c_int32), ("max_active", C.c_int32)]
+
+
 class mclbm_diag_out(C.Structure):
     _fields_ = [("step", C.c_int64), ("momentum", C.c_double * 2), ("ekin", C.c_double),
                 ("max_u", C.c_double), ("nonfinite", C.c_int32)]
@@ -69,6 +73,14 @@ _sig = {
     "mclbm_load": (_i, [_vp, _vp, _i]),
     "mclbm_destroy": (_i, [_vp]),
     "mclbm_last_error": (C.c_char_p, []),
+    "mclbm_server_plan": (_i, [C.POINTER(mclbm_server_config), C.POINTER(_sz)]),
+    "mclbm_server_create": (_i, [C.POINTER(mclbm_server_config), _vp, _sz, _vp, C.POINTER(_vp)]),
+    "mclbm_server_submit": (_i, [_vp, C.POINTER(mclbm_params), C.POINTER(mclbm_side_spec), _vp, _i64, _vp,
+                                 C.POINTER(_i64)]),
+    "mclbm_server_progress": (_i, [_vp, C.POINTER(_i64), C.c_int32, C.POINTER(C.c_int32)]),
+    "mclbm_server_result": (_i, [_vp, _i64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "mclbm_server_counts": (_i, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
+    "mclbm_server_destroy": (_i, [_vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -164,6 +176,51 @@ def mclbm_load(h: int, src_ptr: int, on_device: int) -> None:
 
 def mclbm_destroy(h: int) -> None:
     _lib.mclbm_destroy(_vp(h))
+
+
+def mclbm_server_plan(cfg: mclbm_server_config) -> int:
+    n = _sz(0)
+    _check(_lib.mclbm_server_plan(C.byref(cfg), C.byref(n)), "mclbm_server_plan")
+    return n.value
+
+
+def mclbm_server_create(cfg: mclbm_server_config, pool_ptr: int, pool_bytes: int, stream_ptr: int) -> int:
+    h = _vp()
+    _check(_lib.mclbm_server_create(C.byref(cfg), _vp(pool_ptr), pool_bytes, _vp(stream_ptr), C.byref(h)),
+           "mclbm_server_create")
+    return h.value
+
+
+def mclbm_server_submit(h: int, p: mclbm_params, sides, u0_ptr: Optional[int], nsteps: int,
+                        u_out_ptr: int) -> int:
+    arr = (mclbm_side_spec * 4)(*sides)
+    rid = _i64(0)
+    _check(_lib.mclbm_server_submit(_vp(h), C.byref(p), arr, _vp(u0_ptr), int(nsteps), _vp(u_out_ptr),
+                                    C.byref(rid)), "mclbm_server_submit")
+    return rid.value
+
+
+def mclbm_server_progress(h: int, cap: int = 1024):
+    ids = (_i64 * cap)()
+    n = C.c_int32(0)
+    _check(_lib.mclbm_server_progress(_vp(h), ids, cap, C.byref(n)), "mclbm_server_progress")
+    return [ids[i] for i in range(n.value)]
+
+
+def mclbm_server_result(h: int, rid: int):
+    st, status = C.c_int32(0), C.c_int32(0)
+    _check(_lib.mclbm_server_result(_vp(h), int(rid), C.byref(st), C.byref(status)), "mclbm_server_result")
+    return st.value, status.value
+
+
+def mclbm_server_counts(h: int):
+    w, a, d = _i64(0), _i64(0), _i64(0)
+    _check(_lib.mclbm_server_counts(_vp(h), C.byref(w), C.byref(a), C.byref(d)), "mclbm_server_counts")
+    return w.value, a.value, d.value
+
+
+def mclbm_server_destroy(h: int) -> None:
+    _lib.mclbm_server_destroy(_vp(h))
 
 
 # ---- convenience wrapper (torch owns the device memory and the stream) -------------------------
@@ -273,3 +330,70 @@ def sim_from_workload(w, precision="f64", **kw) -> Sim:
     for side, sd in w.sides.items():
         s.set_side(side, sd.bc, sd.kind, sd.amp, sd.t0, sd.t1, sd.width)
     return s
+
+
+class Server:
+    """A continuous-batching server over a torch-allocated device pool and a
+    stream of its own (graph capture needs one).  ``submit`` queues a request
+    and returns its id; ``progress`` runs one scheduling turn and returns the
+    ids it finished; ``result(id)`` gives (state, status, u) with u the final
+    displacement [2, ny, nx] as a numpy array once done."""
+
+    def __init__(self, precision="f32", steps_per_round=32, max_active=64, pool_bytes=8 << 30,
+                 device="cuda"):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.cfg = mclbm_server_config(PRECISION[precision], int(steps_per_round), int(max_active))
+        self.precision = precision
+        self.reserved = mclbm_server_plan(self.cfg)
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        self._h = mclbm_server_create(self.cfg, self.pool.data_ptr(), int(pool_bytes), self.stream.cuda_stream)
+        self._out: Dict[int, np.ndarray] = {}
+        self._keep: Dict[int, object] = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._h = None
+            try:
+                mclbm_server_destroy(h)
+            except TypeError:  # interpreter shutdown
+                pass
+
+    def submit(self, nx, ny, *, mu, nu, tau, material, sides, nsteps, u0=None, rho0=1.0, dx=1.0,
+               body=(0.0, 0.0)) -> int:
+        """sides: {"left": (bc, kind, amp, t0, t1, width) or bc, ...}; missing sides are free."""
+        p = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=self.precision,
+                        rho0=rho0, dx=dx, body=body)
+        specs = []
+        for name in ("left", "right", "bottom", "top"):
+            spec = sides.get(name, "neumann")
+            args = (spec,) if isinstance(spec, str) else tuple(spec)
+            specs.append(make_side(*args))
+        out = np.empty((2, int(ny), int(nx)), dtype=np.float64)
+        u0a = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float64).reshape(2, ny, nx)
+        rid = mclbm_server_submit(self._h, p, specs, None if u0a is None else u0a.ctypes.data, nsteps,
+                                  out.ctypes.data)
+        self._out[rid] = out
+        return rid
+
+    def progress(self):
+        return mclbm_server_progress(self._h)
+
+    def result(self, rid):
+        state, status = mclbm_server_result(self._h, rid)
+        return state, status, (self._out.get(rid) if state == 2 else None)
+
+    def counts(self):
+        return mclbm_server_counts(self._h)
+
+    def drain(self):
+        """Run turns until every submitted request is done; returns the finished ids in order."""
+        done = []
+        while True:
+            done += self.progress()
+            w, a, _ = self.counts()
+            if w == 0 and a == 0:
+                return done

@@ -135,3 +135,14 @@ def test_copy_argument_errors_without_gpu(M):
         M.mclbm_copy(None, fake, 8, 0)
     assert e.value.code == M.MCLBM_EINVAL
     M.mclbm_copy(None, None, 0, 0)
+
+
+def test_server_config_validation(M):
+    """The server's configuration is checked on the host."""
+    ok = M.mclbm_server_config(M.PRECISION["f32"], 32, 64)
+    assert M.mclbm_server_plan(ok) > 0
+    for bad in [(M.PRECISION["f16"], 32, 64), (M.PRECISION["f32"], 0, 64), (M.PRECISION["f32"], 32, 0),
+                (M.PRECISION["f32"], 2000, 64)]:
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_server_plan(M.mclbm_server_config(*bad))
+        assert e.value.code == M.MCLBM_EINVAL

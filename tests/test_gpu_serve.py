@@ -1,0 +1,147 @@
+"""The continuous-batching server on the GPU, through the C ABI.
+
+- isolation: every request's result is bitwise the same alone and in a mix of
+  lattice sizes, materials, loads and step counts admitted over several rounds;
+  against the plain single-lattice path (mclbm_step) it agrees within the parity
+  bars (the batch cuts a lattice into other row chunks, and a node in a chunk
+  that touches a lattice edge takes the edge copy of the loop, whose rounding
+  can differ in the last bit);
+- admission by memory: a pool with room for two arenas serves a longer queue;
+- the server's FP64 results against the oracle;
+- a diverging request is reported as unstable and does not disturb the rest.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00920_amd import serve as S
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(8, os.cpu_count() or 1)
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def close(u, ref, precision):
+    return np.linalg.norm(u - ref) <= TOL[precision] * np.linalg.norm(ref)
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2502_00920_amd import mclbm
+    return mclbm
+
+
+def small_requests(n, seed):
+    """Short requests of the serving mix with nu in [0, 0.24], inside the bound of
+    first-order boundary stencils: a diverging run would amplify the last-bit
+    differences between decompositions."""
+    reqs = S.make_requests(n, seed=seed, steps=(20, 150), sides=(20, 300))
+    for r in reqs:
+        r["nu"] *= 0.24 / 0.45
+        if r["case"] == "cantilever":  # the pulse needs many steps; shorten its program
+            r["sides"]["right"] = ("neumann", "gauss", (0.0, 1e-3 * r["mu"]), 20, 60, 10)
+    return reqs
+
+
+def alone_via_sim(M, r, precision):
+    s = M.Sim(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"], precision=precision)
+    for name, spec in r["sides"].items():
+        s.set_side(name, *((spec,) if isinstance(spec, str) else tuple(spec)))
+    s.init()
+    s.step(r["nsteps"])
+    return s.read("u")
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_isolation_bitwise(M, precision):
+    print(f"\n[case] server isolation {precision}", flush=True)
+    reqs = small_requests(12, seed=3)
+    sv = M.Server(precision=precision, steps_per_round=8, max_active=5, pool_bytes=256 << 20)
+    ids = [S._submit(sv, r) for r in reqs]
+    seen_active = 0
+    done = []
+    while len(done) < len(ids):
+        done += sv.progress()
+        seen_active = max(seen_active, sv.counts()[1])
+    assert sorted(done) == sorted(ids) and seen_active == 5
+    for r, rid in zip(reqs, ids):
+        state, status, u_mix = sv.result(rid)
+        assert state == 2 and status == 0
+        solo = M.Server(precision=precision, steps_per_round=8, max_active=1, pool_bytes=64 << 20)
+        sid = S._submit(solo, r)
+        solo.drain()
+        u_alone = solo.result(sid)[2]
+        u_sim = alone_via_sim(M, r, precision)
+        assert np.array_equal(u_mix, u_alone), r
+        assert close(u_mix, u_sim, precision), r
+        del solo
+
+
+def test_admission_by_memory(M):
+    print("\n[case] server admission by pool size", flush=True)
+    reqs = small_requests(6, seed=5)
+    for r in reqs:
+        r["nx"] = r["ny"] = 96
+    cfg = M.mclbm_server_config(M.PRECISION["f32"], 4, 64)
+    arena, _ = M.mclbm_plan(M.make_params(96, 96, mu=0.05, nu=0.3, tau=0.55, precision="f32"))
+    pool = M.mclbm_server_plan(cfg) + 2 * ((arena + 255) // 256 * 256)
+    sv = M.Server(precision="f32", steps_per_round=4, max_active=64, pool_bytes=pool)
+    ids = [S._submit(sv, r) for r in reqs]
+    most = 0
+    done = []
+    while len(done) < len(ids):
+        done += sv.progress()
+        most = max(most, sv.counts()[1])
+    assert most == 2
+    for r, rid in zip(reqs, ids):
+        assert close(sv.result(rid)[2], alone_via_sim(M, r, "f32"), "f32")
+
+
+def test_server_against_oracle(M):
+    print("\n[case] server FP64 against the oracle", flush=True)
+    reqs = small_requests(4, seed=7)
+    sv = M.Server(precision="f64", steps_per_round=16, max_active=4, pool_bytes=128 << 20)
+    ids = [S._submit(sv, r) for r in reqs]
+    sv.drain()
+    for r, rid in zip(reqs, ids):
+        o = oracle.Oracle(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
+                          threads=THREADS)
+        for name, spec in r["sides"].items():
+            o.set_side(name, *((spec,) if isinstance(spec, str) else tuple(spec)))
+        o.init()
+        o.step(r["nsteps"])
+        ref = o.read("u")
+        u = sv.result(rid)[2]
+        e = np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)
+        print(r["case"], r["nx"], r["material"], f"{e:.2e}", flush=True)
+        assert e <= 1e-12
+
+
+def test_unstable_request_is_flagged(M):
+    print("\n[case] server flags a diverging request", flush=True)
+    rng = np.random.default_rng(1)
+    bad = dict(nx=32, ny=32, mu=0.05, nu=0.49, tau=0.55, material="svk", nsteps=3000,
+               sides={s: "periodic" for s in ("left", "right", "bottom", "top")})
+    good = small_requests(3, seed=9)
+    sv = M.Server(precision="f32", steps_per_round=32, max_active=8, pool_bytes=64 << 20)
+    u0 = rng.uniform(-1e-3, 1e-3, size=(2, 32, 32))
+    bid = sv.submit(32, 32, mu=0.05, nu=0.49, tau=0.55, material="svk", sides=bad["sides"], nsteps=3000, u0=u0)
+    gids = [S._submit(sv, r) for r in good]
+    sv.drain()
+    s = M.Sim(32, 32, mu=0.05, nu=0.49, tau=0.55, material="svk", precision="f32")
+    for side in ("left", "right", "bottom", "top"):
+        s.set_side(side, "periodic")
+    s.init(u0)
+    s.step(3000)
+    diverged = s.diag()["nonfinite"]
+    assert sv.result(bid)[1] == (M.MCLBM_EUNSTABLE if diverged else M.MCLBM_OK)
+    for r, rid in zip(good, gids):
+        state, status, u = sv.result(rid)
+        assert state == 2 and status == 0
+        assert close(u, alone_via_sim(M, r, "f32"), "f32")
