@@ -13,6 +13,10 @@ import os
 from typing import Dict, Optional
 
 import numpy as np
+# torch first: it loads its own HIP runtime, and the library must bind to that
+# one.  Loaded the other way round, the process holds two HIP runtimes and the
+# library's finds no device.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmclbm.so")

@@ -3,6 +3,8 @@ and rejects bad arguments on the host (no GPU, no kernel launches)."""
 import ctypes as C
 import os
 import re
+import subprocess
+import sys
 
 import pytest
 
@@ -34,6 +36,16 @@ def test_library_exports_every_declared_symbol(M):
     lib = C.CDLL(M.LIB_PATH)
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """Imported before torch, the binding still leaves one HIP runtime in the
+    process (torch's): a second copy would find no device."""
+    code = ("from paper_2502_00920_amd import mclbm\n"
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[-1] == "1"
 
 
 def test_plan_validation(M):
