@@ -1,0 +1,97 @@
+"""The paper's experiments (Sect. 4) on the GPU: parity with the oracle at the
+paper's lattice (dX = 0.025, t = 2.2), and the lattice-refinement trend of the
+grid errors against a finer lattice."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2502_00920_amd import paper_cases as PC
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU test ran without a visible GPU")
+    from paper_2502_00920_amd import mclbm
+    return mclbm
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def make_oracle(name, material, nu, dx):
+    nx, ny, sides, p = PC.case(name, material, nu, dx)
+    o = oracle.Oracle(nx, ny, mu=p["mu"], nu=p["nu"], tau=p["tau"], material=p["material"], rho0=p["rho0"],
+                      dx=p["dx"], threads=min(8, os.cpu_count() or 1))
+    PC.configure(o, sides)
+    o.init()
+    return o
+
+
+def oracle_at(name, material, nu, dx, t):
+    """The oracle's u at time t, interpolated in time over three steps."""
+    o = make_oracle(name, material, nu, dx)
+    n0, w = PC.interpolation_weights(t, dx)
+    o.step(n0)
+    u = w[0] * o.read("u")
+    for k in (1, 2):
+        o.step(1)
+        u += w[k] * o.read("u")
+    return u
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("name,material,nu", [("tension", "svk", 0.25), ("tension", "neohooke", -0.1),
+                                              ("shear", "svk", 0.0), ("shear", "neohooke", 0.2),
+                                              ("wave", "neohooke", 0.2)])
+def test_paper_cases_against_oracle(M, name, material, nu, precision):
+    """Up to the last step that the field at t = 2.2 is interpolated from."""
+    print(f"\n[case] paper {name} {material} nu={nu} {precision}", flush=True)
+    dx = 0.025
+    n = PC.interpolation_weights(2.2, dx)[0] + 2
+    o = make_oracle(name, material, nu, dx)
+    o.step(n)
+    s = PC.make_sim(name, material, nu, dx, precision)
+    s.step(n)
+    e = rel(s.read("u"), o.read("u"))
+    print(f"{e:.2e}", flush=True)
+    assert e <= TOL[precision]
+
+
+def test_refinement_trend(M):
+    """The HIP path's lattices dX = 0.05, 0.025, 0.0125 against the oracle's
+    dX = 0.003125: per halving of dX the rms error falls by more than 1.7 and the
+    maximum error by more than 1.4 (first order, as the first-order wall stencils
+    set it); E2 and Einf are those errors over n and about sqrt(n)."""
+    print("\n[case] refinement study, tension SVK nu = 0.2", flush=True)
+    uref = oracle_at("tension", "svk", 0.2, 0.003125, 2.2)
+    r = PC.refinement("tension", "svk", 0.2, reference=0.003125, reference_u=uref)
+    for row in r["levels"]:
+        print(row, flush=True)
+    lv = r["levels"]
+    assert all(row["finite"] for row in lv) and r["reference_finite"]
+    for a, b in zip(lv, lv[1:]):
+        assert a["rms"] / b["rms"] > 1.7 and a["max"] / b["max"] > 1.4
+    for row in lv:
+        n = round(1 / row["dx"]) ** 2
+        assert row["E2"] * n == pytest.approx(row["rms"], rel=1e-12)
+
+
+def test_wave_error_history(M):
+    """The bending wave at dX = 0.05 against dX = 0.025, both on the HIP path, up
+    to t = 4: every sample finite, errors of the size a first-order lattice
+    gives."""
+    print("\n[case] wave error history", flush=True)
+    r = PC.time_series("wave", "neohooke", 0.2, 0.05, 0.025, 4.0, every=1.0)
+    for smp in r["samples"]:
+        print(smp, flush=True)
+    assert len(r["samples"]) == 4 and all(smp["finite"] for smp in r["samples"])
+    assert all(0 < smp["Einf"] < 0.5 for smp in r["samples"])
