@@ -58,7 +58,7 @@ size_t pop_bytes_per_node(int precision) {
 Layout layout_of(const mclbm_params& p) {
     Layout L;
     L.pitch = (p.nx + 63) / 64 * 64;
-    const size_t plane = (size_t)(p.ny + 1) * L.pitch;  // row ny takes the priming rows' stores
+    const size_t plane = (size_t)p.ny * L.pitch;
     L.f_bytes = align_up(pop_bytes_per_node(p.precision) * plane);
     L.u_bytes = align_up(2 * plane * 8);
     Geometry g{p.nx, p.ny, L.pitch, 0, 0, (long long)plane};
@@ -83,7 +83,7 @@ int check_params(const mclbm_params* p) {
     // the device addresses three FP64 / FP32 planes, four planes of packed 16-bit
     // pairs, or the two displacement planes through one 32-bit buffer range each
     {
-        const int64_t plane = (int64_t)(p->ny + 1) * ((p->nx + 63) / 64 * 64);
+        const int64_t plane = (int64_t)p->ny * ((p->nx + 63) / 64 * 64);
         const int64_t range = p->precision == MCLBM_F64 ? 24 : (p->precision == MCLBM_F32 ? 12 : 16);
         if (plane * range >= ((int64_t)1 << 32) || plane * 2 * 8 >= ((int64_t)1 << 32))
             return fail(MCLBM_EINVAL, "lattice of %d x %d nodes too large for one device buffer range "
@@ -248,7 +248,7 @@ MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_b
     s->L = L;
     s->arena = static_cast<char*>(arena);
     s->stream = static_cast<hipStream_t>(stream);
-    s->g = Geometry{p->nx, p->ny, L.pitch, 0, 0, (long long)(p->ny + 1) * L.pitch};
+    s->g = Geometry{p->nx, p->ny, L.pitch, 0, 0, (long long)p->ny * L.pitch};
     const double c = lattice_speed(*p);
     s->dt = p->dx / c;
     s->k.omega = 1.0 / p->tau;

@@ -23,8 +23,7 @@ struct Geometry {
     int nx, ny;        // nodes
     int pitch;         // row pitch in elements (multiple of 64)
     int px, py;        // periodic in x / y
-    long long plane;   // elements per component plane: (ny + 1) rows; row ny takes
-                       // the stores of the rows that prime a chunk and is never read
+    long long plane;   // elements per component plane: ny rows of pitch
 };
 
 struct Coef {
@@ -80,6 +79,42 @@ __device__ __forceinline__ T feq_q(int q, T r, T m1x, T m1y, T m2xx, T m2xy, T m
     const T e2 = X * X + Y * Y;
     return wq<T>(q) * (r + T(3) * eM1 +
                        T(0.5) * (T(9) * eM2e - T(3) * r * e2 - T(3) * (m2xx + m2yy) + T(2) * r));
+}
+
+// The BGK collision of one node in FP64, written per direction pair: the terms
+// that a direction and its opposite share in the equilibrium above are formed
+// once, the moments share the sums over the diagonal pairs, and the weights are
+// folded into the relaxation factor: fn_q = (1 - omega) f_q + omega w_q X_q with
+// feq_q = w_q X_q.  It equals feq_q above up to the rounding order.
+struct NodeMoments {
+    double r, m1x, m1y;
+};
+__device__ __forceinline__ NodeMoments collide_node(const double F[9], double om1, double ow0, double ow1,
+                                                     double ow5, double fn[9]) {
+    const double a57 = F[5] + F[7], a68 = F[6] + F[8];
+    const double c57 = F[5] - F[7], c86 = F[8] - F[6];
+    const double s24 = F[2] + F[4], dsum = a57 + a68;
+    const double m2xx = (F[1] + F[3]) + dsum, m2yy = s24 + dsum, m2xy = a57 - a68;
+    const double m1x = (F[1] - F[3]) + (c57 + c86);
+    const double m1y = (F[2] - F[4]) + (c57 - c86);
+    const double r = F[0] + (m2xx + s24);
+    const double S = m2xx + m2yy;
+    const double X0 = 2.0 * r - 1.5 * S;        // rest
+    const double b1 = 0.5 * r - 1.5 * S;        // axis directions, before their own terms
+    const double Px = b1 + 4.5 * m2xx, Py = b1 + 4.5 * m2yy;
+    const double Dg = 3.0 * S - r;              // diagonal directions
+    const double Dp = Dg + 9.0 * m2xy, Dm = Dg - 9.0 * m2xy;
+    const double ppl = m1x + m1y, pmi = m1x - m1y;
+    fn[0] = om1 * F[0] + ow0 * X0;
+    fn[1] = om1 * F[1] + ow1 * (Px + 3.0 * m1x);
+    fn[3] = om1 * F[3] + ow1 * (Px - 3.0 * m1x);
+    fn[2] = om1 * F[2] + ow1 * (Py + 3.0 * m1y);
+    fn[4] = om1 * F[4] + ow1 * (Py - 3.0 * m1y);
+    fn[5] = om1 * F[5] + ow5 * (Dp + 3.0 * ppl);
+    fn[7] = om1 * F[7] + ow5 * (Dp - 3.0 * ppl);
+    fn[6] = om1 * F[6] + ow5 * (Dm - 3.0 * pmi);
+    fn[8] = om1 * F[8] + ow5 * (Dm + 3.0 * pmi);
+    return NodeMoments{r, m1x, m1y};
 }
 
 // ---- materials, Sect. 4 (plane strain) ------------------------------------------------

@@ -6,7 +6,7 @@
 
 namespace mclbm {
 
-// Populations: [9][ny + 1][pitch] of double or float, or for 16-bit storage four
+// Populations: [9][ny][pitch] of double or float, or for 16-bit storage four
 // planes of 32-bit words (word w: population 2w in the low half, 2w + 1 in the
 // high half) followed by one plane of population 8 (16-bit values).
 struct StepArgs {

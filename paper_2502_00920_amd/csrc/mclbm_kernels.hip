@@ -178,8 +178,8 @@ __device__ __forceinline__ V from_next(V v, V edge) { return dpp_shift<kDppWaveS
 // registers the rows r..r+3 of u, r..r+2 of T, r-1..r+1 of sigma and r-1..r+1
 // of the populations, and the loads of the rows D iterations ahead are in
 // flight (D prefetch sets, so that no register holding a pending load is
-// renamed; every iteration issues the same loads and stores in the same order,
-// so the waits stay counted).  x neighbours come from lane shifts, y
+// renamed; every iteration issues the same loads in the same order, so the
+// waits stay counted; only the two rows that prime a chunk skip their stores).  x neighbours come from lane shifts, y
 // neighbours from the rows held.
 //
 // What lanes 0 and 63 need from beyond the strip (u of x0-1 and x0+64, their
@@ -193,17 +193,17 @@ __device__ __forceinline__ V from_next(V v, V edge) { return dpp_shift<kDppWaveS
 // Waves whose rows and halo columns stay off the lattice edges (no clamping,
 // wrapping or one-sided differences) run a copy of the loop without those
 // selects.  Elsewhere, lanes beyond nx compute on clamped (or, periodic,
-// wrapped) data and store into the row padding; rows that prime the pipeline
-// store into row ny.
+// wrapped) data and store into the row padding; the rows that prime a chunk
+// store nothing.
 
 template <typename T, typename TS, int HR>
 struct Halo {  // rows k = 0..HR+5 of a block are rows r0 - 3 + k
     static constexpr int HK = HR + 6;
-    double u[2][HK][5][2];  // [side][k][column c][comp]; side 0: x0-3+c, side 1: x0+62+c
+    double u[2][HK][5][2];  // [side][k][column c][comp]; side 0: x0-3+c, side 1: x0+62+c;
+                            // iteration rel reads c = 2 of row r0 + rel + 2 (k = rel + 5)
     TS t[2][HK][3][4];      // T at c = 1, 2, 3
     TS s[2][HK][2];         // sigma at c = 2
     // what iteration rel of the block reads, side by side
-    double un[2][HR][2];    // u at c = 2, row r0 + rel + 2
     TS tn[2][HR][4];        // T at c = 2, row r0 + rel + 1
     T hn[2][HR][4];         // pull sources at c = 2: side 0 p = 1, 5, 8 from rows
                             // r0+rel, r0+rel-1, r0+rel+1; side 1 p = 3, 6, 7 likewise
@@ -247,8 +247,9 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
     constexpr int NRAW = PK ? 5 : 9;
     constexpr int HK = HR + 6;
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);  // iterations per loop trip
-    constexpr int NU = 5 * HK, NT = 3 * (HK - 2), NS = HK - 4;         // halo items per side
-    static_assert(2 * NU <= 128 && NU <= 64 && 2 * NT <= 64 && 6 * NS <= 64 && HR >= 1 && D >= 1,
+    // halo items per side: u of a whole block and of its new rows, T, sigma
+    constexpr int NU = 5 * HK, NUN = 5 * HR, NT = 3 * (HK - 2), NS = HK - 4;
+    static_assert(NU <= 64 && 2 * NT <= 64 && 2 * NS <= 64 && 6 * HR <= 64 && HR >= 1 && D >= 1,
                   "halo block too long for one wave");
     const Geometry g = a.g;
     const int x0 = strip * 64;
@@ -279,7 +280,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
     const TS ic2 = TS(a.k.inv_c2), sbx = TS(a.k.sig_b[0]), sby = TS(a.k.sig_b[1]);
     const TS lam = TS(a.k.lam), mu = TS(a.k.mu);
     const double omd = a.k.omega;
-    const uint32_t trash = (uint32_t)(g.ny * g.pitch + vx);  // row ny: written, never read
+    const double om1 = 1.0 - omd, ow0 = omd * wq<double>(0), ow1 = omd * wq<double>(1), ow5 = omd * wq<double>(5);
 
     auto run = [&](auto edge_flag) {
         constexpr bool EDGE = decltype(edge_flag)::value;
@@ -403,20 +404,28 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         };
 
         // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
+        //
+        // A block's rows k = 0..5 are rows HR..HR+5 of the block before, so after the
+        // first block of a chunk only the HR new rows of u are gathered and the rest
+        // is moved within the LDS.  Each pulled population is gathered on the HR rows
+        // whose pulls use it (pull i of row rel comes from row rel + hrow(i)).
         double gu[2][2];  // u gathered for the next halo pass: [side][comp]
         Raw gf;           // population gathered for it (raw; packed: the word holding it)
+        // lane j < 6 HR: the halo population of side j / (3 HR), pull (j / HR) % 3, row j % HR
+        auto hrow = [](int pi) { return pi == 0 ? 3 : (pi == 1 ? 2 : 4); };  // its block row k - rel
         // where this lane's halo population sits in a packed word: the high half?
         // (population 8: the parity of its column, as the row pitch is even)
         const bool ghigh = [&] {
-            const int j = min(lane, 6 * NS - 1);
-            const int sd = j / (3 * NS);
-            const int p = halo_pop(sd, (j % (3 * NS)) / NS);
+            const int j = min(lane, 6 * HR - 1);
+            const int sd = j / (3 * HR);
+            const int p = halo_pop(sd, (j % (3 * HR)) / HR);
             const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
             return p == 8 ? (hx & 1) != 0 : (p & 1) != 0;
         }();
-        auto gather_all = [&](int r0) {
-            const int i = min(lane, NU - 1);
-            const int c = i % 5, k = i / 5;
+        // u: all rows of the block (full, the first block of a chunk) or its new ones
+        auto gather = [&](int r0, bool full) {
+            const int i = min(lane, (full ? NU : NUN) - 1);
+            const int c = i % 5, k = (full ? 0 : 6) + i / 5;
             const int rr = rowp(r0 - 3 + k);
 #pragma unroll
             for (int sd = 0; sd < 2; sd++) {
@@ -425,8 +434,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 gu[sd][0] = bload(rus, ob, 0u, 0.0);
                 gu[sd][1] = bload(rus, ob, pbD, 0.0);
             }
-            const int j = min(lane, 6 * NS - 1);
-            const int sd = j / (3 * NS), pi = (j % (3 * NS)) / NS, k2 = 2 + j % NS;
+            const int j = min(lane, 6 * HR - 1);
+            const int sd = j / (3 * HR), pi = (j % (3 * HR)) / HR, k2 = j % HR + hrow(pi);
             const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
             const int p = halo_pop(sd, pi);
             const size_t o = (size_t)rowp(r0 - 3 + k2) * g.pitch + hx;
@@ -438,18 +447,42 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 gf = reinterpret_cast<const ST*>(fs)[(size_t)p * plane + o];
             }
         };
-        auto halo = [&](int r0) {
+        auto halo = [&](int r0, bool full) {
             wave_lds_sync();  // the last block's reads come first
-            if (lane < NU) {
-                const int c = lane % 5, k = lane / 5;
+            if (full) {
+                if (lane < NU) {
+                    const int c = lane % 5, k = lane / 5;
 #pragma unroll
-                for (int sd = 0; sd < 2; sd++) {
-                    hl.u[sd][k][c][0] = gu[sd][0];
-                    hl.u[sd][k][c][1] = gu[sd][1];
-                    // u at c = 2 for the iteration that needs it: row r0 + rel + 2, k = rel + 5
-                    if (c == 2 && k >= 5 && k < 5 + HR) {
-                        hl.un[sd][k - 5][0] = gu[sd][0];
-                        hl.un[sd][k - 5][1] = gu[sd][1];
+                    for (int sd = 0; sd < 2; sd++) {
+                        hl.u[sd][k][c][0] = gu[sd][0];
+                        hl.u[sd][k][c][1] = gu[sd][1];
+                    }
+                }
+            } else {
+                // rows HR..HR+5 of the last block become rows 0..5 (every lane reads
+                // before any lane writes: one LDS read, then the writes, in order)
+                double mv[2][2];
+                const int c = lane % 5, k = lane / 5;
+                if (lane < 30) {
+#pragma unroll
+                    for (int sd = 0; sd < 2; sd++) {
+                        mv[sd][0] = hl.u[sd][k + HR][c][0];
+                        mv[sd][1] = hl.u[sd][k + HR][c][1];
+                    }
+                }
+                wave_lds_sync();
+                if (lane < 30) {
+#pragma unroll
+                    for (int sd = 0; sd < 2; sd++) {
+                        hl.u[sd][k][c][0] = mv[sd][0];
+                        hl.u[sd][k][c][1] = mv[sd][1];
+                    }
+                }
+                if (lane < NUN) {
+#pragma unroll
+                    for (int sd = 0; sd < 2; sd++) {
+                        hl.u[sd][6 + k][c][0] = gu[sd][0];
+                        hl.u[sd][6 + k][c][1] = gu[sd][1];
                     }
                 }
             }
@@ -498,8 +531,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 hl.s[sd][k][1] = ic2 * ((byx - ayx) * fx + (dyy - cyy) * fy) + sby;
             }
             wave_lds_sync();
-            if (lane < 6 * NS) {  // pull sources: the population plus dt psi at the source
-                const int sd = lane / (3 * NS), pi = (lane % (3 * NS)) / NS, k = 2 + lane % NS;
+            if (lane < 6 * HR) {  // pull sources: the population plus dt psi at the source
+                const int sd = lane / (3 * HR), pi = (lane % (3 * HR)) / HR, rel = lane % HR, k = rel + hrow(pi);
                 const int p = halo_pop(sd, pi);
                 T fp;
                 if constexpr (PK) fp = SF::dec(ghigh ? (gf >> 16) : gf) * finv;
@@ -507,8 +540,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 const T hv = fp + T(3) * wq<T>(p) * T(TS(ex(p)) * hl.s[sd][k][0] + TS(ey(p)) * hl.s[sd][k][1]);
                 // the iteration pulling it: p = 1, 3 from its own row (k = rel + 3),
                 // p = 5, 6 from the row before (k = rel + 2), p = 7, 8 from the row after
-                const int rel = k - (pi == 0 ? 3 : (pi == 1 ? 2 : 4));
-                if (rel >= 0 && rel < HR) hl.hn[sd][rel][pi] = hv;
+                hl.hn[sd][rel][pi] = hv;
             }
             wave_lds_sync();
         };
@@ -621,9 +653,6 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         static_assert(L % DD == 0, "prefetch sets must divide the loop trip");
         double UP[DD][2];
         Raw FP[DD][NRAW];
-        T zero9[9];
-#pragma unroll
-        for (int q = 0; q < 9; q++) zero9[q] = T(0);
 
         // iteration r, the block's relative row rel (0..HR-1)
         auto iteration = [&](int r, int rel, double Us[2], Raw Fs[NRAW]) {
@@ -632,8 +661,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             decode(Fs, F1);
             load_u(r + 3 + DD, Us);
             load_f(r + 1 + DD, Fs);
-            const double ul[2] = {hl.un[0][rel][0], hl.un[0][rel][1]};
-            const double ur[2] = {hl.un[1][rel][0], hl.un[1][rel][1]};
+            const double ul[2] = {hl.u[0][rel + 5][2][0], hl.u[0][rel + 5][2][1]};
+            const double ur[2] = {hl.u[1][rel + 5][2][0], hl.u[1][rel + 5][2][1]};
             TS T2[4], G1[2];
             stress(r + 2, U1, U2, U3, T2, ul, ur);
             TS tl[4], tr[4];
@@ -679,29 +708,22 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             // weights are not exact in FP32 (3 (2 w1 + 4 w5) rounds to 1 + 7.5e-9),
             // so an FP32 equilibrium scales j and Pi by about 1 + omega 7.5e-9 in
             // every collision, a bias that compounds over the steps.
-            double rho = 0, m1x = 0, m1y = 0, m2xx = 0, m2xy = 0, m2yy = 0;
-            double o1x = 0, o1y = 0;
+            double fd[9], fnd[9];
 #pragma unroll
-            for (int q = 0; q < 9; q++) {
-                const double fq = (double)f[q], gq = (double)F0[q];
-                rho += fq;
-                if (ex(q)) m1x += ex(q) * fq;
-                if (ey(q)) m1y += ey(q) * fq;
-                if (ex(q)) m2xx += fq;
-                if (ex(q) * ey(q)) m2xy += (ex(q) * ey(q)) * fq;
-                if (ey(q)) m2yy += fq;
-                if (ex(q)) o1x += ex(q) * gq;
-                if (ey(q)) o1y += ey(q) * gq;
-            }
-            const uint32_t node = (r >= yc && r < ye) ? (uint32_t)(r * g.pitch + vx) : trash;
+            for (int q = 0; q < 9; q++) fd[q] = (double)f[q];
+            const NodeMoments mo = collide_node(fd, om1, ow0, ow1, ow5, fnd);
+            const double m1x = mo.m1x, m1y = mo.m1y;
+            // first moment of the node's own populations before streaming (j_n)
+            const double g57 = (double)F0[5] - (double)F0[7], g86 = (double)F0[8] - (double)F0[6];
+            const double o1x = ((double)F0[1] - (double)F0[3]) + (g57 + g86);
+            const double o1y = ((double)F0[2] - (double)F0[4]) + (g57 - g86);
             T fn[9];
 #pragma unroll
-            for (int q = 0; q < 9; q++) {
-                const double e = feq_q<double>(q, rho, m1x, m1y, m2xx, m2xy, m2yy);
-                fn[q] = T((double)f[q] + omd * (e - (double)f[q]));
-            }
-            store_node(node, U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
-                       U0[1] + a.k.ucoef * (m1y + o1y + (double)G0[1]), fn);
+            for (int q = 0; q < 9; q++) fn[q] = T(fnd[q]);
+            // the two rows that prime the chunk store nothing (wave-uniform)
+            if (r >= yc && r < ye)
+                store_node((uint32_t)(r * g.pitch + vx), U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
+                           U0[1] + a.k.ucoef * (m1y + o1y + (double)G0[1]), fn);
 
             U0[0] = U1[0]; U0[1] = U1[1];
             U1[0] = U2[0]; U1[1] = U2[1];
@@ -715,11 +737,11 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         };
 
         // prime: the halo of the first block (waited for here, once per chunk), the
-        // rows, the prefetch sets each followed by the stores an iteration issues,
-        // and the gathers of the next block, in the order the loop repeats
+        // rows, the prefetch sets and the gathers of the next block, in the order
+        // the loop repeats
         int r0 = yc - 2;
-        gather_all(r0);
-        halo(r0);
+        gather(r0, true);
+        halo(r0, true);
         load_u(yc - 3, tmp);
         load_u(yc - 2, U0);
         load_u(yc - 1, U1);
@@ -728,9 +750,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         for (int i = 0; i < DD; i++) {
             load_u(yc + 1 + i, UP[i]);
             load_f(yc - 1 + i, FP[i]);
-            store_node(trash, 0.0, 0.0, zero9);
         }
-        gather_all(r0 + HR);
+        gather(r0 + HR, false);
         {
             // T of the rows yc-2 (k = 3) and yc-1 (k = 4) of the first block
             const double l3[2] = {hl.u[0][3][2][0], hl.u[0][3][2][1]}, r3[2] = {hl.u[1][3][2][0], hl.u[1][3][2][1]};
@@ -747,8 +768,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 iteration(r0 + j % HR, j % HR, UP[j % DD], FP[j % DD]);
                 if (j % HR == HR - 1) {
                     r0 += HR;
-                    halo(r0);
-                    gather_all(r0 + HR);
+                    halo(r0, false);
+                    gather(r0 + HR, false);
                 }
             }
         }
