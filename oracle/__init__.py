@@ -59,6 +59,7 @@ def lib() -> C.CDLL:
         L.orc_set_threads.argtypes = [vp, i]
         L.orc_set_extrap_linear.argtypes = [vp, i]
         L.orc_set_listing_order.argtypes = [vp, i]
+        L.orc_set_boundary_order.argtypes = [vp, i]
         L.orc_set_side.restype = i
         L.orc_set_side.argtypes = [vp, i, i, i, d, d, d, d, d]
         L.orc_init.argtypes = [vp, dp, dp]
@@ -144,7 +145,7 @@ class Oracle:
     """One simulation on the CPU.  Fields come back as [comp, ny, nx] arrays."""
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", rho0=1.0, dx=1.0,
-                 body=(0.0, 0.0), threads=1, extrap="copy", order="text"):
+                 body=(0.0, 0.0), threads=1, extrap="copy", order="text", boundary_order=1):
         self.nx, self.ny = int(nx), int(ny)
         self._h = lib().orc_create(self.nx, self.ny, dx, rho0, mu, nu, tau,
                                    MATERIAL[material], body[0], body[1])
@@ -153,6 +154,9 @@ class Oracle:
         lib().orc_set_threads(self._h, int(threads))
         lib().orc_set_extrap_linear(self._h, 1 if extrap == "linear" else 0)
         lib().orc_set_listing_order(self._h, 1 if order == "listing" else 0)
+        if boundary_order not in (1, 2):
+            raise ValueError("boundary_order is 1 or 2")
+        lib().orc_set_boundary_order(self._h, int(boundary_order))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -38,7 +38,8 @@
  *     therefore sees S_{n-1}, is kept as an option (time_levels = 1).
  *   - Nodes are cell centred, walls lie half way to the next (absent) node.
  *   - Finite differences: central in the interior, first-order one-sided
- *     (using the inward neighbour) at the outermost node.
+ *     (using the inward neighbour) at the outermost node.  Second-order
+ *     one-sided differences there are an option (boundary order 2).
  *   - Neumann momentum flux at the wall (Sect. 3.3): with outward normal
  *     N = s e_a and tangential axis b, Pi_aa = -s T*_a + ext(T_aa),
  *     Pi_ab = Pi_ba = -s T*_b + ext(T_ba), Pi_bb = ext(Pi_bb of the
@@ -84,7 +85,7 @@ typedef struct {
 } side_t;
 
 typedef struct {
-    int nx, ny, material, extrap_linear, listing_order, threads;
+    int nx, ny, material, extrap_linear, listing_order, boundary_order, threads;
     double dx, rho0, mu, nu, tau, body[2];
     /* derived, Sect. 3.2 */
     double lam, cs2, c, dt, omega;
@@ -288,6 +289,7 @@ void *orc_create(int nx, int ny, double dx, double rho0, double mu, double nu,
     h->nx = nx; h->ny = ny; h->dx = dx; h->rho0 = rho0; h->mu = mu; h->nu = nu;
     h->tau = tau; h->material = material; h->body[0] = bx; h->body[1] = by;
     h->threads = 1;
+    h->boundary_order = 1;
     h->lam = orc_lambda(mu, nu);
     h->cs2 = mu / rho0;                        /* c_s = sqrt(mu/rho0), Sect. 3.1 */
     h->c = sqrt(3.0) * sqrt(h->cs2);           /* c = sqrt(3) c_s, Sect. 3.2 */
@@ -327,6 +329,11 @@ void orc_set_extrap_linear(void *hv, int on) { ((orc_t *)hv)->extrap_linear = on
 /* 0: stresses at level n (default); 1: the printed order of Algorithm 1. */
 void orc_set_listing_order(void *hv, int on) { ((orc_t *)hv)->listing_order = on ? 1 : 0; }
 
+/* 1: first-order one-sided differences at the outermost nodes (Sect. 3.2, the
+ * scheme's own); 2: second-order one-sided ones, the boundary stencils for which
+ * the CFL discussion of Sect. 3.2 would admit nu <= 5/11 (an option). */
+void orc_set_boundary_order(void *hv, int order) { ((orc_t *)hv)->boundary_order = order == 2 ? 2 : 1; }
+
 int orc_set_side(void *hv, int side, int bc, int kind, double ax, double ay,
                  double t0, double t1, double width)
 {
@@ -354,10 +361,15 @@ static double fd(const orc_t *h, const double *v, int x, int y, int axis)
     double div;
     if (per) {
         mp = (m + 1) % L; mm = (m - 1 + L) % L; div = 2.0 * h->dx;
-    } else if (m == 0) {
-        mp = 1; mm = 0; div = h->dx;
-    } else if (m == L - 1) {
-        mp = L - 1; mm = L - 2; div = h->dx;
+    } else if (m == 0 || m == L - 1) {
+        /* one-sided: first order with the inward neighbour, or second order,
+         * (-3 v_0 + 4 v_1 - v_2) / (2 dX) mirrored at the far side */
+        int s = m == 0 ? 1 : -1;
+#define AT(k) (axis == 0 ? v[IDX(h, m + s * (k), y)] : v[IDX(h, x, m + s * (k))])
+        if (h->boundary_order == 2)
+            return s * (-3.0 * AT(0) + 4.0 * AT(1) - AT(2)) / (2.0 * h->dx);
+        return s * (AT(1) - AT(0)) / h->dx;
+#undef AT
     } else {
         mp = m + 1; mm = m - 1; div = 2.0 * h->dx;
     }

@@ -273,6 +273,46 @@ def test_finite_difference_rules():
     np.testing.assert_allclose(H[3], 3.0, rtol=1e-15)
 
 
+def test_second_order_boundary_differences():
+    """The option of Sect. 3.2's CFL remark: second-order one-sided differences at
+    the outermost nodes, exact for quadratics (u = (x^2 + 2 y^2, x y)), where the
+    first-order ones are off by dX at a quadratic's boundary nodes."""
+    nx, ny = 7, 6
+    X, Y = nodes(nx, ny)
+    u0 = np.stack([X ** 2 + 2 * Y ** 2, X * Y])
+    exact = [2 * X, 4 * Y, Y, X]  # H = (d ux/dX, d ux/dY, d uy/dX, d uy/dY)
+    o = make(nx, ny, {s: "neumann" for s in W.SIDES}, boundary_order=2)
+    o.init(u0)
+    H = o.read("h")
+    for k in range(4):
+        np.testing.assert_allclose(H[k], exact[k], rtol=1e-14, atol=1e-13)
+    o1 = make(nx, ny, {s: "neumann" for s in W.SIDES})
+    o1.init(u0)
+    H1 = o1.read("h")
+    assert abs(H1[0][2, 0] - exact[0][2, 0]) == pytest.approx(1.0, rel=1e-13)  # d/dX of x^2, dX = 1
+    np.testing.assert_allclose(H1[0][:, 1:-1], exact[0][:, 1:-1], rtol=1e-14)
+    with pytest.raises(ValueError):
+        make(nx, ny, {s: "neumann" for s in W.SIDES}, boundary_order=3)
+
+
+def test_second_order_boundary_differences_lose_stability():
+    """Sect. 3.2 argues that second-order stencils at the boundary would admit nu
+    up to 5/11.  Plain second-order one-sided differences do the opposite here: the
+    traction-loaded tension case of Sect. 4.1 (dX = 0.025, mu = 1, to t = 2.2) stays
+    bounded at nu = 0.4 with the scheme's first-order stencils and diverges with
+    second-order ones.  This is why the kernels keep the first-order stencils."""
+    from paper_2502_00920_amd import paper_cases as PC
+    for order, stable in ((1, True), (2, False)):
+        nx, ny, sides, p = PC.case("tension", "svk", 0.4, 0.025)
+        o = PC.configure(oracle.Oracle(nx, ny, mu=p["mu"], nu=p["nu"], tau=p["tau"], material=p["material"],
+                                       rho0=p["rho0"], dx=p["dx"], threads=4, boundary_order=order), sides)
+        o.init()
+        o.step(PC.steps_for(2.2, 0.025))
+        u = o.read("u")
+        bounded = bool(np.all(np.isfinite(u)) and np.abs(u).max() < 1.0)
+        assert bounded == stable, order
+
+
 def test_periodic_differences_wrap():
     nx, ny = 8, 6
     X, Y = nodes(nx, ny)
