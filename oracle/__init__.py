@@ -60,6 +60,8 @@ def lib() -> C.CDLL:
         L.orc_set_extrap_linear.argtypes = [vp, i]
         L.orc_set_listing_order.argtypes = [vp, i]
         L.orc_set_boundary_order.argtypes = [vp, i]
+        L.orc_set_tau_plus.argtypes = [vp, d]
+        L.orc_collide_trt.argtypes = [d, dp, d, d, d, dp, dp, dp, dp, dp, dp]
         L.orc_set_side.restype = i
         L.orc_set_side.argtypes = [vp, i, i, i, d, d, d, d, d]
         L.orc_init.argtypes = [vp, dp, dp]
@@ -120,6 +122,15 @@ def collide(cs2, cq, omega, dt, f, S):
     return out, float(r[0]), j, Pi
 
 
+def collide_trt(cs2, cq, omega, omega_plus, dt, f, S):
+    """One-node two-relaxation-time collision with forcing (the option):
+    (f_coll, r, j, Pi(xx, xy, yy))."""
+    out, r, j, Pi = np.zeros(9), np.zeros(1), np.zeros(2), np.zeros(3)
+    lib().orc_collide_trt(cs2, _p(_f64(cq)), omega, omega_plus, dt, _p(_f64(f)), _p(_f64(S)), _p(out),
+                          _p(r), _p(j), _p(Pi))
+    return out, float(r[0]), j, Pi
+
+
 def plane_strain_lambda(mu, nu):
     return lib().orc_lambda(mu, nu)
 
@@ -145,7 +156,8 @@ class Oracle:
     """One simulation on the CPU.  Fields come back as [comp, ny, nx] arrays."""
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", rho0=1.0, dx=1.0,
-                 body=(0.0, 0.0), threads=1, extrap="copy", order="text", boundary_order=1):
+                 body=(0.0, 0.0), threads=1, extrap="copy", order="text", boundary_order=1,
+                 tau_plus=None):
         self.nx, self.ny = int(nx), int(ny)
         self._h = lib().orc_create(self.nx, self.ny, dx, rho0, mu, nu, tau,
                                    MATERIAL[material], body[0], body[1])
@@ -157,6 +169,10 @@ class Oracle:
         if boundary_order not in (1, 2):
             raise ValueError("boundary_order is 1 or 2")
         lib().orc_set_boundary_order(self._h, int(boundary_order))
+        if tau_plus is not None:
+            if not tau_plus > 0.5:
+                raise ValueError("tau_plus must exceed 0.5")
+            lib().orc_set_tau_plus(self._h, float(tau_plus))
 
     def __del__(self):
         h = getattr(self, "_h", None)

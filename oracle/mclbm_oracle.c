@@ -52,6 +52,7 @@
  *     crosses two Neumann walls uses a combined Pi_bd (normal entries from
  *     each wall, shear entry the mean of both).
  *   - Initial state: f = f_eq(r0 = -rho0 tr H(u0), j0, Pi(H(u0))).
+ *   - Collision: BGK (the paper's); two relaxation times as an option.
  * Periodic sides are an addition for tests (momentum balance, plane waves).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared -o liboracle.so
@@ -89,6 +90,7 @@ typedef struct {
     double dx, rho0, mu, nu, tau, body[2];
     /* derived, Sect. 3.2 */
     double lam, cs2, c, dt, omega;
+    double omega_plus; /* two-relaxation-time option: rate of the even part, 0 = BGK */
     double cq[9][2]; /* physical lattice velocities c_q = c * e_q */
     side_t side[4];
     /* state at the start of step n */
@@ -152,6 +154,40 @@ void orc_collide(double cs2, const double cq[9][2], double omega, double dt,
     orc_psi(cs2, cq, S, psi);
     for (int q = 0; q < 9; q++)
         out[q] = f[q] - omega * (f[q] - feq[q]) + (1.0 - 0.5 * omega) * psi[q] * dt;
+    if (r_out) *r_out = r;
+    if (j_out) { j_out[0] = jj[0]; j_out[1] = jj[1]; }
+    if (Pi_out) { Pi_out[0] = pxx; Pi_out[1] = pxy; Pi_out[2] = pyy; }
+}
+
+/* The same collision with two relaxation times (an option; the paper names
+ * collision operators beyond BGK as a way to stability, Sect. 6): the
+ * non-equilibrium part n = f - f_eq splits into its even part (n_q + n_qbar)/2,
+ * relaxed at omega_plus, and its odd part (n_q - n_qbar)/2, relaxed at omega as
+ * in BGK; the forcing, odd, keeps the factor (1 - omega/2).  With
+ * omega_plus = omega this is the BGK collision above. */
+void orc_collide_trt(double cs2, const double cq[9][2], double omega, double omega_plus, double dt,
+                     const double f[9], const double S[2], double out[9],
+                     double *r_out, double j_out[2], double Pi_out[3])
+{
+    double r = 0, mx = 0, my = 0, pxx = 0, pxy = 0, pyy = 0;
+    for (int q = 0; q < 9; q++) {
+        r += f[q];
+        mx += cq[q][0] * f[q];
+        my += cq[q][1] * f[q];
+        pxx += cq[q][0] * cq[q][0] * f[q];
+        pxy += cq[q][0] * cq[q][1] * f[q];
+        pyy += cq[q][1] * cq[q][1] * f[q];
+    }
+    double jj[2] = {mx + 0.5 * dt * S[0], my + 0.5 * dt * S[1]};
+    double Pi3[3] = {pxx, pxy, pyy};
+    double feq[9], psi[9];
+    orc_feq(cs2, cq, r, jj, Pi3, feq);
+    orc_psi(cs2, cq, S, psi);
+    for (int q = 0; q < 9; q++) {
+        double nq = f[q] - feq[q], nb = f[OPP[q]] - feq[OPP[q]];
+        double even = 0.5 * (nq + nb), odd = 0.5 * (nq - nb);
+        out[q] = f[q] - omega_plus * even - omega * odd + (1.0 - 0.5 * omega) * psi[q] * dt;
+    }
     if (r_out) *r_out = r;
     if (j_out) { j_out[0] = jj[0]; j_out[1] = jj[1]; }
     if (Pi_out) { Pi_out[0] = pxx; Pi_out[1] = pxy; Pi_out[2] = pyy; }
@@ -334,6 +370,10 @@ void orc_set_listing_order(void *hv, int on) { ((orc_t *)hv)->listing_order = on
  * the CFL discussion of Sect. 3.2 would admit nu <= 5/11 (an option). */
 void orc_set_boundary_order(void *hv, int order) { ((orc_t *)hv)->boundary_order = order == 2 ? 2 : 1; }
 
+/* tau_plus > 0.5: collide with two relaxation times (orc_collide_trt), the even
+ * part at 1 / tau_plus; otherwise BGK. */
+void orc_set_tau_plus(void *hv, double tau_plus) { ((orc_t *)hv)->omega_plus = tau_plus > 0.5 ? 1.0 / tau_plus : 0.0; }
+
 int orc_set_side(void *hv, int side, int bc, int kind, double ax, double ay,
                  double t0, double t1, double width)
 {
@@ -493,7 +533,10 @@ static void step_once(orc_t *h)
             double fl[9], fcl[9], r, jj[2], Pi3[3];
             for (int q = 0; q < 9; q++) fl[q] = h->f[q * N + i];
             double Sl[2] = {S[i], S[N + i]};
-            orc_collide(cs2, h->cq, om, dt, fl, Sl, fcl, &r, jj, Pi3);
+            if (h->omega_plus > 0)
+                orc_collide_trt(cs2, h->cq, om, h->omega_plus, dt, fl, Sl, fcl, &r, jj, Pi3);
+            else
+                orc_collide(cs2, h->cq, om, dt, fl, Sl, fcl, &r, jj, Pi3);
             h->jA[i] = jj[0]; h->jA[N + i] = jj[1];
             h->r[i] = r;
             h->Pi[i] = Pi3[0]; h->Pi[N + i] = Pi3[1]; h->Pi[2 * N + i] = Pi3[2];

@@ -3,7 +3,8 @@
 Each test fixes one piece of the method against mathematics the paper states or
 implies, independently of how the oracle writes it:
   - D2Q9 equilibrium and forcing reproduce their moments (Sect. 3.2, Tab. 1)
-  - BGK collision keeps r and Pi and adds dt*S to the momentum (Algorithm 1)
+  - BGK collision keeps r and Pi and adds dt*S to the momentum (Algorithm 1);
+    the two-relaxation-time option relaxes its odd and even moments at its two rates
   - St. Venant-Kirchhoff and neo-Hooke stresses (Sect. 4) against hand-derived
     closed forms for simple shear and uniaxial stress, objectivity, hyperelastic
     energy derivatives and their linearisation
@@ -85,6 +86,47 @@ def test_collision_relaxes_to_equilibrium_at_tau_one():
     fc, r, j, Pi = oracle.collide(cs2, cq, 1.0, dt, f, S)
     expect = oracle.feq(cs2, cq, r, j, Pi) + 0.5 * dt * oracle.psi(cs2, cq, S)
     np.testing.assert_allclose(fc, expect, atol=1e-14)
+
+
+def moments34(cq, g):
+    """The odd third-order moments (xxy, xyy) and the even fourth-order one (xxyy)."""
+    cx, cy = cq[:, 0], cq[:, 1]
+    return np.array([np.sum(cx * cx * cy * g), np.sum(cx * cy * cy * g)]), np.sum(cx * cx * cy * cy * g)
+
+
+def test_trt_collision_with_equal_rates_is_bgk():
+    cs2, c, dt, cq = lat(0.05)
+    rng = np.random.default_rng(11)
+    f = rng.normal(size=9)
+    S = rng.normal(size=2)
+    for tau in (0.55, 1.0, 1.7):
+        a = oracle.collide(cs2, cq, 1.0 / tau, dt, f, S)
+        b = oracle.collide_trt(cs2, cq, 1.0 / tau, 1.0 / tau, dt, f, S)
+        np.testing.assert_allclose(b[0], a[0], atol=1e-14)
+        np.testing.assert_allclose(b[2], a[2], atol=1e-15)
+
+
+@pytest.mark.parametrize("tau,tau_plus", [(0.55, 1.0), (0.55, 0.7), (1.2, 0.6)])
+def test_trt_collision_moments(tau, tau_plus):
+    """Two relaxation times: r and Pi are kept and the momentum gains dt S, as in
+    BGK; the odd third-order non-equilibrium moments relax by (1 - 1/tau), the
+    even fourth-order one by (1 - 1/tau_plus)."""
+    cs2, c, dt, cq = lat(0.05)
+    rng = np.random.default_rng(5)
+    f = rng.normal(size=9)
+    S = rng.normal(size=2)
+    fc, r, j, Pi = oracle.collide_trt(cs2, cq, 1.0 / tau, 1.0 / tau_plus, dt, f, S)
+    assert abs(fc.sum() - f.sum()) < 1e-14
+    np.testing.assert_allclose(np.einsum("qa,qb,q->ab", cq, cq, fc),
+                               np.einsum("qa,qb,q->ab", cq, cq, f), atol=1e-14)
+    np.testing.assert_allclose(cq.T @ fc, cq.T @ f + dt * S, atol=1e-13)
+    # without a source the equilibrium of the result is that of f
+    fc, r, j, Pi = oracle.collide_trt(cs2, cq, 1.0 / tau, 1.0 / tau_plus, dt, f, np.zeros(2))
+    feq = oracle.feq(cs2, cq, r, j, Pi)
+    odd_in, even_in = moments34(cq, f - feq)
+    odd_out, even_out = moments34(cq, fc - feq)
+    np.testing.assert_allclose(odd_out, (1 - 1 / tau) * odd_in, atol=1e-15 * c ** 3)
+    assert even_out == pytest.approx((1 - 1 / tau_plus) * even_in, abs=1e-15 * c ** 4)
 
 
 # ---- material laws, Sect. 4 ----------------------------------------------------
