@@ -124,6 +124,14 @@ typedef struct {
     double nu;            /* Poisson ratio in (-1, 0.5); lambda = 2 mu nu/(1-2nu)*/
     double tau;           /* relaxation time in units of dt, > 0.5              */
     double body[2];       /* body force b per unit mass                         */
+    double tau_plus;      /* 0: BGK collision (the paper's).  > 0.5: two
+                           * relaxation times, an option for stability (the
+                           * paper's conclusion, Sect. 6, names collision
+                           * operators beyond BGK): the non-equilibrium part
+                           * n = f - f_eq splits into its odd part
+                           * (n_q - n_qbar)/2, relaxed at 1/tau as in BGK, and
+                           * its even part (n_q + n_qbar)/2, relaxed at
+                           * 1/tau_plus.  tau_plus = tau is BGK.                */
 } mclbm_params;
 
 typedef struct {

@@ -92,6 +92,8 @@ int check_params(const mclbm_params* p) {
     if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
         return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");
     if (!(p->tau > 0.5)) return fail(MCLBM_EINVAL, "tau must exceed 0.5 (got %g)", p->tau);
+    if (!(p->tau_plus == 0.0 || p->tau_plus > 0.5))
+        return fail(MCLBM_EINVAL, "tau_plus must be 0 (BGK) or exceed 0.5 (got %g)", p->tau_plus);
     if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(MCLBM_EINVAL, "nu must lie in (-1, 0.5) (got %g)", p->nu);
     if (p->material < MCLBM_SVK || p->material > MCLBM_LINEAR)
         return fail(MCLBM_EINVAL, "unknown material %d", p->material);
@@ -252,6 +254,7 @@ MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_b
     const double c = lattice_speed(*p);
     s->dt = p->dx / c;
     s->k.omega = 1.0 / p->tau;
+    s->k.omega_p = p->tau_plus > 0.5 ? 1.0 / p->tau_plus : s->k.omega;
     s->k.c = c;
     s->k.inv_c = 1.0 / c;
     s->k.inv_c2 = 1.0 / (c * c);

@@ -28,6 +28,7 @@ struct Geometry {
 
 struct Coef {
     double omega;     // dt / tau, tau in units of dt
+    double omega_p;   // rate of the even non-equilibrium part (omega: BGK)
     double c;         // lattice speed dX/dt
     double inv_c;     // 1/c
     double inv_c2;    // 1/c^2 = dt^2/dX^2 = rho0/(3 mu)
@@ -81,16 +82,40 @@ __device__ __forceinline__ T feq_q(int q, T r, T m1x, T m1y, T m2xx, T m2xy, T m
                        T(0.5) * (T(9) * eM2e - T(3) * r * e2 - T(3) * (m2xx + m2yy) + T(2) * r));
 }
 
-// The BGK collision of one node in FP64, written per direction pair: the terms
-// that a direction and its opposite share in the equilibrium above are formed
-// once, the moments share the sums over the diagonal pairs, and the weights are
-// folded into the relaxation factor: fn_q = (1 - omega) f_q + omega w_q X_q with
-// feq_q = w_q X_q.  It equals feq_q above up to the rounding order.
+// The collision of one node in FP64, written per direction pair q, qbar.  The
+// non-equilibrium part n = f - feq relaxes with two rates: its odd part
+// (n_q - n_qbar)/2 at omega (the paper's BGK rate) and its even part at
+// omega_p (omega_p = omega is BGK; other values are the two-relaxation-time
+// option).  With feq_q = w_q X_q, A = (omega_p + omega)/2, B = (omega_p - omega)/2:
+//   fn_q = (1 - A) f_q - B f_qbar + w_q (omega_p E_q + omega O_q),
+// where E and O are the parts of X even and odd under q -> qbar.  The terms a
+// direction shares with its opposite are formed once, the moments share the sums
+// over the diagonal pairs, and the weights fold into the rates.  The result
+// equals the relaxation towards feq_q above up to the rounding order.
+struct CollideRates {
+    double oa;         // 1 - A
+    double b;          // B (0 for BGK)
+    double ep0, ep1, ep5;  // omega_p w_q
+    double od1, od5;   // 3 omega w_q
+    double o0;         // 1 - omega_p
+};
+__host__ __device__ inline CollideRates collide_rates(double omega, double omega_p) {
+    CollideRates k;
+    k.oa = 1.0 - 0.5 * (omega_p + omega);
+    k.b = 0.5 * (omega_p - omega);
+    k.ep0 = omega_p * (4.0 / 9.0);
+    k.ep1 = omega_p * (1.0 / 9.0);
+    k.ep5 = omega_p * (1.0 / 36.0);
+    k.od1 = 3.0 * omega * (1.0 / 9.0);
+    k.od5 = 3.0 * omega * (1.0 / 36.0);
+    k.o0 = 1.0 - omega_p;
+    return k;
+}
 struct NodeMoments {
     double r, m1x, m1y;
 };
-__device__ __forceinline__ NodeMoments collide_node(const double F[9], double om1, double ow0, double ow1,
-                                                     double ow5, double fn[9]) {
+template <bool TWO_RATES>
+__device__ __forceinline__ NodeMoments collide_node(const double F[9], const CollideRates& k, double fn[9]) {
     const double a57 = F[5] + F[7], a68 = F[6] + F[8];
     const double c57 = F[5] - F[7], c86 = F[8] - F[6];
     const double s24 = F[2] + F[4], dsum = a57 + a68;
@@ -105,15 +130,27 @@ __device__ __forceinline__ NodeMoments collide_node(const double F[9], double om
     const double Dg = 3.0 * S - r;              // diagonal directions
     const double Dp = Dg + 9.0 * m2xy, Dm = Dg - 9.0 * m2xy;
     const double ppl = m1x + m1y, pmi = m1x - m1y;
-    fn[0] = om1 * F[0] + ow0 * X0;
-    fn[1] = om1 * F[1] + ow1 * (Px + 3.0 * m1x);
-    fn[3] = om1 * F[3] + ow1 * (Px - 3.0 * m1x);
-    fn[2] = om1 * F[2] + ow1 * (Py + 3.0 * m1y);
-    fn[4] = om1 * F[4] + ow1 * (Py - 3.0 * m1y);
-    fn[5] = om1 * F[5] + ow5 * (Dp + 3.0 * ppl);
-    fn[7] = om1 * F[7] + ow5 * (Dp - 3.0 * ppl);
-    fn[6] = om1 * F[6] + ow5 * (Dm - 3.0 * pmi);
-    fn[8] = om1 * F[8] + ow5 * (Dm + 3.0 * pmi);
+    const double Ex = k.ep1 * Px, Ox = k.od1 * m1x, Ey = k.ep1 * Py, Oy = k.od1 * m1y;
+    const double Ep = k.ep5 * Dp, Op = k.od5 * ppl, Em = k.ep5 * Dm, Om = k.od5 * pmi;
+    fn[0] = k.o0 * F[0] + k.ep0 * X0;
+    fn[1] = k.oa * F[1] + (Ex + Ox);
+    fn[3] = k.oa * F[3] + (Ex - Ox);
+    fn[2] = k.oa * F[2] + (Ey + Oy);
+    fn[4] = k.oa * F[4] + (Ey - Oy);
+    fn[5] = k.oa * F[5] + (Ep + Op);
+    fn[7] = k.oa * F[7] + (Ep - Op);
+    fn[6] = k.oa * F[6] + (Em - Om);
+    fn[8] = k.oa * F[8] + (Em + Om);
+    if constexpr (TWO_RATES) {  // the even part's rate differs from omega
+        fn[1] -= k.b * F[3];
+        fn[3] -= k.b * F[1];
+        fn[2] -= k.b * F[4];
+        fn[4] -= k.b * F[2];
+        fn[5] -= k.b * F[7];
+        fn[7] -= k.b * F[5];
+        fn[6] -= k.b * F[8];
+        fn[8] -= k.b * F[6];
+    }
     return NodeMoments{r, m1x, m1y};
 }
 

@@ -14,7 +14,9 @@
 //      modified bounce-back / anti-bounce-back rules of Sect. 3.3 from the
 //      node's own post-collision populations and T_n(X)
 //   4. u_{n+1} = u_n + dt/(2 rho0) (j(t_{n+1}) + j(t_n)), both j carrying S_n
-//   5. fc'_{n+1} = (1 - omega) f + omega f_eq(r, M1, M2)
+//   5. fc'_{n+1} = f - omega odd(f - f_eq) - omega_p even(f - f_eq), f_eq =
+//      f_eq(r, M1, M2): BGK for omega_p = omega (the paper's), two relaxation
+//      times otherwise
 // A step is one launch of march_kernel: one pass over HBM, each wave owning 64
 // aligned columns of a band of rows; the waves that touch a lattice edge apply
 // the wall rules to their wall nodes.
@@ -280,10 +282,12 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
     const TS ic2 = TS(a.k.inv_c2), sbx = TS(a.k.sig_b[0]), sby = TS(a.k.sig_b[1]);
     const TS lam = TS(a.k.lam), mu = TS(a.k.mu);
     const double omd = a.k.omega;
-    const double om1 = 1.0 - omd, ow0 = omd * wq<double>(0), ow1 = omd * wq<double>(1), ow5 = omd * wq<double>(5);
+    const CollideRates crk = collide_rates(omd, a.k.omega_p);
+    const bool two_rates = a.k.omega_p != omd;
 
-    auto run = [&](auto edge_flag) {
+    auto run = [&](auto edge_flag, auto two_rates_flag) {
         constexpr bool EDGE = decltype(edge_flag)::value;
+        constexpr bool TWO_RATES = decltype(two_rates_flag)::value;
         // row / column -> row / column to address: periodic wrap, else clamped
         auto rowp = [&](int r) -> int {
             if constexpr (EDGE) return g.py ? wrap(r, g.ny) : min(max(r, 0), g.ny - 1);
@@ -711,7 +715,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             double fd[9], fnd[9];
 #pragma unroll
             for (int q = 0; q < 9; q++) fd[q] = (double)f[q];
-            const NodeMoments mo = collide_node(fd, om1, ow0, ow1, ow5, fnd);
+            const NodeMoments mo = collide_node<TWO_RATES>(fd, crk, fnd);
             const double m1x = mo.m1x, m1y = mo.m1y;
             // first moment of the node's own populations before streaming (j_n)
             const double g57 = (double)F0[5] - (double)F0[7], g86 = (double)F0[8] - (double)F0[6];
@@ -774,8 +778,14 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             }
         }
     };
-    if (inner_x && inner_y) run(Flag<false>{});
-    else run(Flag<true>{});
+    // copies of the loop: edge or interior, BGK or two relaxation times
+    if (inner_x && inner_y) {
+        if (two_rates) run(Flag<false>{}, Flag<true>{});
+        else run(Flag<false>{}, Flag<false>{});
+    } else {
+        if (two_rates) run(Flag<true>{}, Flag<true>{});
+        else run(Flag<true>{}, Flag<false>{});
+    }
 }
 
 // The step of one lattice: one work item per wave.

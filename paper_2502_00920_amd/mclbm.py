@@ -42,7 +42,7 @@ class mclbm_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("material", C.c_int32),
                 ("precision", C.c_int32), ("dx", C.c_double), ("rho0", C.c_double),
                 ("mu", C.c_double), ("nu", C.c_double), ("tau", C.c_double),
-                ("body", C.c_double * 2)]
+                ("body", C.c_double * 2), ("tau_plus", C.c_double)]
 
 
 class mclbm_side_spec(C.Structure):
@@ -230,12 +230,13 @@ def mclbm_server_destroy(h: int) -> None:
 # ---- convenience wrapper (torch owns the device memory and the stream) -------------------------
 
 def make_params(nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0, dx=1.0,
-                body=(0.0, 0.0)) -> mclbm_params:
+                body=(0.0, 0.0), tau_plus=0.0) -> mclbm_params:
     p = mclbm_params()
     p.nx, p.ny = int(nx), int(ny)
     p.material, p.precision = MATERIAL[material], PRECISION[precision]
     p.dx, p.rho0, p.mu, p.nu, p.tau = float(dx), float(rho0), float(mu), float(nu), float(tau)
     p.body[0], p.body[1] = float(body[0]), float(body[1])
+    p.tau_plus = float(tau_plus or 0.0)
     return p
 
 
@@ -252,12 +253,12 @@ class Sim:
     [comp, ny, nx] on the device (or numpy arrays with ``host=True``)."""
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0,
-                 dx=1.0, body=(0.0, 0.0), device="cuda", stream=None):
+                 dx=1.0, body=(0.0, 0.0), tau_plus=0.0, device="cuda", stream=None):
         import torch
         self.torch = torch
         self.nx, self.ny = int(nx), int(ny)
         self.params = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material,
-                                  precision=precision, rho0=rho0, dx=dx, body=body)
+                                  precision=precision, rho0=rho0, dx=dx, body=body, tau_plus=tau_plus)
         self.arena_bytes, self.dt = mclbm_plan(self.params)
         self.device = torch.device(device)
         self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
@@ -367,10 +368,10 @@ class Server:
                 pass
 
     def submit(self, nx, ny, *, mu, nu, tau, material, sides, nsteps, u0=None, rho0=1.0, dx=1.0,
-               body=(0.0, 0.0)) -> int:
+               body=(0.0, 0.0), tau_plus=0.0) -> int:
         """sides: {"left": (bc, kind, amp, t0, t1, width) or bc, ...}; missing sides are free."""
         p = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=self.precision,
-                        rho0=rho0, dx=dx, body=body)
+                        rho0=rho0, dx=dx, body=body, tau_plus=tau_plus)
         specs = []
         for name in ("left", "right", "bottom", "top"):
             spec = sides.get(name, "neumann")

@@ -3,16 +3,19 @@
 The request stream: square lattices with sides log-uniform in [64, 1024];
 St. Venant-Kirchhoff or neo-Hooke with equal odds; nu uniform in [0, 0.45];
 mu = 0.05, tau = 0.55; step counts uniform in [1000, 20000]; one of three load
-cases, each on the walls of the paper's experiments (Sect. 4):
-  tension     left held, right pulled at 3.2e-3 dX per step for the first two
-              thirds of the steps and then held, top and bottom free
-  shear       bottom held, top pulled sideways at 6.4e-3 dX per step for the
-              first half of the steps and then held, left and right free
+cases, each on the walls of the paper's experiments (Sect. 4), with loads that
+scale with the lattice but move no wall faster than a slow pull:
+  tension     left held, right pulled at constant speed over the first two
+              thirds of the steps, then held; it moves by 5 % of the side (a 5 %
+              stretch) or, if that needs more, by 3.2e-3 dX per step
+  shear       bottom held, top moved sideways over the first half of the steps,
+              then held; by 5 % of the side (shear 0.05) or at most 6.4e-3 dX per
+              step; left and right free
   cantilever  left held, transverse Gaussian traction pulse on the right (peak
               1e-3 mu, width 200 steps, centred at step 800, free after 1600)
-Arrivals are Poisson.  Runs with nu above 1/4 may lose stability (first-order
-boundary stencils, Sect. 3.2); they are reported as unstable and left out of
-the latency figures.
+Arrivals are Poisson.  Runs with nu above 1/4 break the CFL bound of first-order
+boundary stencils (Sect. 3.2) and most of them diverge, as do some long runs at
+nu near 0; they are reported as unstable and left out of the latency figures.
 
   python -m paper_2502_00920_amd.serve [--requests 1000] [--seed 0]
       [--steps-min 1000] [--steps-max 20000] [--load 0.8] [--baseline 40]
@@ -40,11 +43,13 @@ def make_requests(n, seed=0, steps=(1000, 20000), sides=(64, 1024), mu=0.05, tau
         nsteps = int(rng.integers(steps[0], steps[1] + 1))
         if case == "tension":
             t1 = max(1, (2 * nsteps) // 3)
-            walls = {"left": ("dirichlet",), "right": ("dirichlet", "disp_ramp", (3.2e-3 * t1, 0.0), 0, t1),
+            d = min(0.05 * side, 3.2e-3 * t1)
+            walls = {"left": ("dirichlet",), "right": ("dirichlet", "disp_ramp", (d, 0.0), 0, t1),
                      "bottom": "neumann", "top": "neumann"}
         elif case == "shear":
             t1 = max(1, nsteps // 2)
-            walls = {"bottom": ("dirichlet",), "top": ("dirichlet", "disp_ramp", (6.4e-3 * t1, 0.0), 0, t1),
+            d = min(0.05 * side, 6.4e-3 * t1)
+            walls = {"bottom": ("dirichlet",), "top": ("dirichlet", "disp_ramp", (d, 0.0), 0, t1),
                      "left": "neumann", "right": "neumann"}
         else:
             walls = {"left": ("dirichlet",), "right": ("neumann", "gauss", (0.0, 1e-3 * mu), 800, 1600, 200),

@@ -37,11 +37,11 @@ def rel(a, b):
 
 
 def pair(M, nx, ny, sides, *, material, mu=0.05, nu=0.3, tau=0.55, precision="f64", u0=None,
-         j0=None, rho0=1.0, dx=1.0, body=(0.0, 0.0), threads=THREADS):
+         j0=None, rho0=1.0, dx=1.0, body=(0.0, 0.0), threads=THREADS, tau_plus=None):
     o = oracle.Oracle(nx, ny, mu=mu, nu=nu, tau=tau, material=material, rho0=rho0, dx=dx,
-                      body=body, threads=threads)
+                      body=body, threads=threads, tau_plus=tau_plus)
     s = M.Sim(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=precision, rho0=rho0,
-              dx=dx, body=body)
+              dx=dx, body=body, tau_plus=tau_plus or 0.0)
     for side, spec in sides.items():
         args = (spec,) if isinstance(spec, str) else tuple(spec)
         o.set_side(side, *args)
@@ -105,6 +105,32 @@ def test_random_state_parity(M, nx, ny, code, material, precision):
         if precision == "f64":
             for f, v in e.items():
                 assert v <= TOL["f64"], (n, f, v, e0)
+        else:
+            assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny,code,material,tau_plus", [
+    (300, 300, "DNDN", "svk", 1.0),      # interior and edge waves
+    (150, 37, "NNNN", "neohooke", 1.0),
+    (65, 17, "PPPP", "neohooke", 0.7),
+    (257, 129, "NDND", "linear", 1.6),
+])
+def test_two_relaxation_times_parity(M, nx, ny, code, material, tau_plus, precision):
+    """The two-relaxation-time option against the oracle's, on random states."""
+    print_case(f"two relaxation times {nx}x{ny} {code} {material} tau_plus={tau_plus} {precision}")
+    u0 = W.smooth_field(nx, ny, 0.05, seed=nx + 2 * ny)
+    j0 = W.random_field(nx, ny, 1e-3, seed=nx * ny + 1)
+    o, s = pair(M, nx, ny, walls(code), material=material, nu=0.2, precision=precision, u0=u0, j0=j0,
+                tau_plus=tau_plus)
+    for n in (1, 9, 30):
+        o.step(n - o.n)
+        s.step(n - s.n)
+        e = compare(o, s)
+        print(n, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+        if precision == "f64":
+            for f, v in e.items():
+                assert v <= TOL["f64"], (n, f, v)
         else:
             assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"], (n, e)
 

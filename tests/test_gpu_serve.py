@@ -123,6 +123,33 @@ def test_server_against_oracle(M):
         assert e <= 1e-12
 
 
+def test_server_two_relaxation_times(M):
+    """Requests with the two-relaxation-time option, in a mix with BGK ones,
+    against the oracle (FP64)."""
+    print("\n[case] server with two relaxation times", flush=True)
+    reqs = small_requests(4, seed=11)
+    sv = M.Server(precision="f64", steps_per_round=16, max_active=4, pool_bytes=128 << 20)
+    ids = []
+    for i, r in enumerate(reqs):
+        tp = 1.0 if i % 2 == 0 else 0.0
+        r["tau_plus"] = tp
+        ids.append(sv.submit(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
+                             sides=r["sides"], nsteps=r["nsteps"], tau_plus=tp))
+    sv.drain()
+    for r, rid in zip(reqs, ids):
+        o = oracle.Oracle(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
+                          threads=THREADS, tau_plus=r["tau_plus"] or None)
+        for name, spec in r["sides"].items():
+            o.set_side(name, *((spec,) if isinstance(spec, str) else tuple(spec)))
+        o.init()
+        o.step(r["nsteps"])
+        ref = o.read("u")
+        u = sv.result(rid)[2]
+        e = np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)
+        print(r["case"], r["nx"], r["material"], r["tau_plus"], f"{e:.2e}", flush=True)
+        assert e <= 1e-12
+
+
 def test_unstable_request_is_flagged(M):
     print("\n[case] server flags a diverging request", flush=True)
     rng = np.random.default_rng(1)
