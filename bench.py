@@ -233,6 +233,46 @@ def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
     return out
 
 
+def config_table() -> dict:
+    """Per-configuration step rates: the GPU (MLUPS over a timed run of each
+    storage mode; the small lattices are cache-resident, so these are effective
+    rates, not roofline figures) and the CPU oracle on this host at one thread and
+    at all of them (the CPU-baseline leg, on short samples of each)."""
+    import torch
+    import oracle
+    from paper_2502_00920_amd import mclbm
+    from paper_2502_00920_amd import workloads as W
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cfgs = [(W.tension32(), ("f64", "f32"), 3000, 300),
+            (W.shear128(0.25), ("f64", "f32"), 2000, 200),
+            (W.beam2048(), ("f64", "f32", "f16"), 2000, 100),
+            (W.tension_large(1024, 1000), ("f64", "f32", "f16"), 1000, 100)]
+    out = {"host_threads": threads, "rows": []}
+    for w, modes, gsteps, osteps in cfgs:
+        row = {"workload": w.name, "nodes": w.nx * w.ny}
+        for m in modes:
+            s = mclbm.sim_from_workload(w, precision=m)
+            s.init()
+            s.step(10)
+            torch.cuda.synchronize()
+            ms = s.step_timed(gsteps)
+            row[f"gpu_{m}_mlups"] = w.nx * w.ny / ms / 1e3
+            del s
+        torch.cuda.empty_cache()
+        for t in (1, threads):
+            o = oracle.Oracle(w.nx, w.ny, mu=w.mu, nu=w.nu, tau=w.tau, material=w.material, threads=t)
+            for side, sd in w.sides.items():
+                o.set_side(side, sd.bc, sd.kind, sd.amp, sd.t0, sd.t1, sd.width)
+            o.init()
+            t0 = time.perf_counter()
+            o.step(osteps)
+            row[f"oracle_{t}t_mlups"] = w.nx * w.ny * osteps / (time.perf_counter() - t0) / 1e6
+        print("# " + json.dumps(row), file=sys.stderr, flush=True)
+        out["rows"].append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +282,8 @@ def main():
     ap.add_argument("--mode", choices=["all", "f32", "f64", "f16", "bf16"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--configs", action="store_true",
+                    help="print the per-configuration rates (GPU and CPU oracle) as one JSON line and exit")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic file from two rocprofv3 --pmc runs of this script and exit")
     args = ap.parse_args()
@@ -257,6 +299,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+
+    if args.configs:
+        print(json.dumps(config_table()), flush=True)
+        return
 
     modes = ["f32", "f64", "f16", "bf16"] if args.mode == "all" else [args.mode]
     results, fields = {}, {}

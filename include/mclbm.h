@@ -147,6 +147,11 @@ typedef struct {
     double ekin;          /* sum_X |j|^2 / (2 rho0), j as MCLBM_FIELD_J          */
     double max_u;         /* max_X |u_n|                                        */
     int32_t nonfinite;    /* 1 when any u or j is NaN or infinite               */
+    int32_t cfl_excess;   /* 1 when the dilatational wave speed exceeds the
+                           * lattice speed, c_d > c, i.e. nu > 1/4: beyond the
+                           * CFL bound of first-order boundary stencils
+                           * (Sect. 3.2).  A warning about the parameters, not
+                           * an error: such runs often diverge near walls.     */
 } mclbm_diag_out;
 
 typedef struct mclbm_sim mclbm_sim; /* opaque host-side handle */

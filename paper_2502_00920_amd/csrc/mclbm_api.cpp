@@ -491,6 +491,8 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
     out->ekin = h[2];
     out->max_u = std::sqrt(h[3]);
     out->nonfinite = h[4] != 0.0;
+    // c_d^2 = (lambda + 2 mu) / rho0 against c^2 = 3 mu / rho0
+    out->cfl_excess = 2.0 * s->p.mu * s->p.nu / (1.0 - 2.0 * s->p.nu) > s->p.mu;
     if (out->nonfinite) return fail(MCLBM_EUNSTABLE, "non-finite u or j at step %lld", (long long)s->n);
     return MCLBM_OK;
 }

@@ -56,7 +56,7 @@ class mclbm_server_config(C.Structure):
 
 class mclbm_diag_out(C.Structure):
     _fields_ = [("step", C.c_int64), ("momentum", C.c_double * 2), ("ekin", C.c_double),
-                ("max_u", C.c_double), ("nonfinite", C.c_int32)]
+                ("max_u", C.c_double), ("nonfinite", C.c_int32), ("cfl_excess", C.c_int32)]
 
 
 _vp, _i, _i64, _sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
@@ -317,7 +317,8 @@ class Sim:
     def diag(self) -> Dict:
         d = mclbm_diag(self._h)
         return {"step": d.step, "momentum": np.array([d.momentum[0], d.momentum[1]]),
-                "ekin": d.ekin, "max_u": d.max_u, "nonfinite": bool(d.nonfinite)}
+                "ekin": d.ekin, "max_u": d.max_u, "nonfinite": bool(d.nonfinite),
+                "cfl_excess": bool(d.cfl_excess)}
 
     def save(self):
         buf = self.torch.empty(mclbm_state_bytes(self._h), dtype=self.torch.uint8, device=self.device)

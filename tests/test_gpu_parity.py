@@ -439,7 +439,7 @@ def test_diag_parity(M):
     o.step(15)
     s.step(15)
     d, od = s.diag(), o.diag()
-    assert d["step"] == 15 and not d["nonfinite"]
+    assert d["step"] == 15 and not d["nonfinite"] and not d["cfl_excess"]  # nu = 0.2 <= 1/4
     np.testing.assert_allclose(d["momentum"], o.momentum(), rtol=1e-11, atol=1e-15)
     assert d["ekin"] == pytest.approx(od["ekin"], rel=1e-11)
     assert d["max_u"] == pytest.approx(od["max_u"], rel=1e-12)
@@ -454,3 +454,4 @@ def test_diag_flags_nonfinite(M):
     s.step(3000)
     d = s.diag()
     assert d["nonfinite"] or d["max_u"] > 1e3
+    assert d["cfl_excess"]  # nu = 0.45 > 1/4
