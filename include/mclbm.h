@@ -243,6 +243,10 @@ const char* mclbm_last_error(void);
  * server collects finished simulations (copying their displacement to the
  * caller's buffer) and admits waiting requests in arrival order while a slot
  * is free and their arena (mclbm_plan bytes) fits in the caller's pool.
+ * After every round a scan of each active simulation's displacement flags the
+ * ones that are no longer finite; they finish at the next turn as
+ * MCLBM_EUNSTABLE instead of running out their steps (the instabilities of
+ * Sect. 3.2 and Sect. 4: CFL excess, large strain).
  *
  * Ownership: the caller owns the device pool (256-byte aligned) and the
  * stream.  The server keeps the first mclbm_server_plan bytes of the pool for
@@ -288,6 +292,10 @@ int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int32_t cap, int3
  * MCLBM_EUNSTABLE when its final state holds non-finite values, or the error
  * that stopped it. */
 int mclbm_server_result(mclbm_server* sv, int64_t id, int32_t* state, int32_t* status);
+
+/* Steps a request has run: nsteps when it finished normally, fewer when it was
+ * stopped as unstable or failed.  EINVAL for an unknown id. */
+int mclbm_server_steps(mclbm_server* sv, int64_t id, int64_t* steps);
 
 /* Requests waiting, in flight and done so far (any pointer may be NULL). */
 int mclbm_server_counts(mclbm_server* sv, int64_t* waiting, int64_t* active, int64_t* done);

@@ -422,6 +422,16 @@ void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e) {
     e->pad_ = 0;
 }
 
+void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e) {
+    const int c = (s->cur + (int)(k & 1)) & 1;
+    e->u = static_cast<const double*>(at(s, s->L.off_u[c]));
+    e->plane = s->g.plane;
+    e->nx = s->g.nx;
+    e->ny = s->g.ny;
+    e->pitch = s->g.pitch;
+    e->slot = slot;
+}
+
 // record k steps taken outside mclbm_step
 void advance(mclbm_sim* s, int64_t k) {
     s->n += k;

@@ -66,6 +66,17 @@ inline size_t batch_step_bytes(int max_sims) {
     return (sizeof(BatchStep) + (size_t)(max_sims - 1) * sizeof(BatchEntry) + 255) / 256 * 256;
 }
 
+// One lattice's displacement for the batching server's failure scan: u at
+// [2][ny][pitch]; the scan raises flags[slot] if any u of a node is not finite.
+struct ScanEntry {
+    const double* u;
+    long long plane;
+    int nx, ny, pitch, slot;
+};
+// scan n entries (a table in device memory) into flags (device memory, cleared
+// by the caller); a fixed grid, so the launch costs the same for any batch
+hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStream_t st);
+
 // work items of one lattice's step in a batch: 64-column strips times row chunks
 void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk);
 // the step for every simulation of one material in the table at step (device
@@ -82,6 +93,8 @@ namespace mclbm {
 // step counter advanced by k steps taken in batches, the thread's error message
 void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e);
 void advance(mclbm_sim* s, int64_t k);
+// the scan entry of s's displacement after k more steps
+void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e);
 int set_error(int code, const char* msg);
 
 // prec: PREC_F64 / F32 / F16 / BF16.  One launch: march_kernel over every node,

@@ -1034,6 +1034,36 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int n
     if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// Failure scan of the batching server: every node of every listed lattice, both
+// displacement components; a wave that sees a value that is not finite raises its
+// lattice's flag with one lane's buffer store (a vector store: no scalar-cache
+// writes; concurrent stores all write 1).
+constexpr int kScanBlocks = 1024;
+
+__global__ __launch_bounds__(256) void nanscan_kernel(const ScanEntry* __restrict__ tab, int n,
+                                                      uint32_t* __restrict__ flags) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t nthreads = gridDim.x * blockDim.x;
+    for (int e = 0; e < n; e++) {
+        const ScanEntry s = tab[e];
+        const uint32_t nodes = (uint32_t)s.nx * (uint32_t)s.ny, nx = (uint32_t)s.nx;
+        bool bad = false;
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nodes; i += nthreads) {
+            const size_t o = (size_t)(i / nx) * (size_t)s.pitch + i % nx;
+            bad |= !isfinite(s.u[o]) || !isfinite(s.u[(size_t)s.plane + o]);
+        }
+        const uint64_t any = __builtin_amdgcn_ballot_w64(bad);
+        if (any && lane == (int)__builtin_ctzll(any))
+            __builtin_amdgcn_raw_buffer_store_b32(1u, rsrc(flags + s.slot, 4), 0u, 0u, 0);
+    }
+}
+
+hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nanscan_kernel, dim3(kScanBlocks), dim3(256), 0, st, tab, n, flags);
+    return hipGetLastError();
+}
+
 // ---- launchers ---------------------------------------------------------------------------------
 
 // rows per chunk of march_kernel: a multiple of its iterations per loop trip

@@ -16,6 +16,9 @@
 // admits waiting requests in arrival order while a slot is free and their
 // arena fits in the caller's device pool (first fit).  Requests that arrive
 // while others are on the GPU join at the next round and share its launches.
+// After each round a scan of every active simulation's displacement flags the
+// ones that hold values that are not finite; they end at the next turn as
+// unstable instead of running out their steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -90,6 +93,7 @@ struct Request {
     mclbm_sim* sim = nullptr;
     int64_t done_steps = 0;
     int64_t round_steps = 0;
+    int slot = -1;  // its entry in the round's failure scan
 };
 
 }  // namespace
@@ -103,6 +107,8 @@ struct mclbm_server {
     size_t pool_bytes = 0;
     hipStream_t stream = nullptr;
     size_t step_bytes = 0, table_bytes = 0;
+    size_t scan_off = 0, flags_off = 0, reserved_bytes = 0;  // in the reserved head of the pool
+    uint32_t* host_flags = nullptr;                             // pinned: the round's scan flags
     Heap heap;
     char* host_table = nullptr;  // pinned staging of one round's tables
     int64_t next_id = 1;
@@ -131,6 +137,16 @@ int check_config(const mclbm_server_config* c) {
 
 // table of step k, group g
 size_t table_off(const mclbm_server* sv, int k, int g) { return ((size_t)k * kGroups + g) * sv->step_bytes; }
+
+// the reserved head of the pool: the step tables of a round, the failure-scan
+// table and its flags (uploaded together, the flags as zeros)
+void layout_reserved(const mclbm_server_config* c, size_t* tables, size_t* scan_off, size_t* flags_off,
+                     size_t* total) {
+    *tables = (size_t)c->steps_per_round * kGroups * batch_step_bytes(c->max_active);
+    *scan_off = *tables;
+    *flags_off = *scan_off + align_up((size_t)c->max_active * sizeof(ScanEntry));
+    *total = *flags_off + align_up((size_t)c->max_active * sizeof(uint32_t));
+}
 
 void release(mclbm_server* sv, Request& r) {
     if (r.sim) {
@@ -188,7 +204,9 @@ int capture(mclbm_server* sv, int gi) {
 
 MCLBM_EXPORT int mclbm_server_plan(const mclbm_server_config* cfg, size_t* reserved_bytes) {
     if (int rc = check_config(cfg)) return rc;
-    if (reserved_bytes) *reserved_bytes = (size_t)cfg->steps_per_round * kGroups * batch_step_bytes(cfg->max_active);
+    size_t tables, scan, flags, total;
+    layout_reserved(cfg, &tables, &scan, &flags, &total);
+    if (reserved_bytes) *reserved_bytes = total;
     return MCLBM_OK;
 }
 
@@ -207,14 +225,16 @@ MCLBM_EXPORT int mclbm_server_create(const mclbm_server_config* cfg, void* pool,
     sv->pool_bytes = pool_bytes;
     sv->stream = static_cast<hipStream_t>(stream);
     sv->step_bytes = batch_step_bytes(cfg->max_active);
-    sv->table_bytes = (size_t)cfg->steps_per_round * kGroups * sv->step_bytes;
-    if (pool_bytes < sv->table_bytes) {
+    layout_reserved(cfg, &sv->table_bytes, &sv->scan_off, &sv->flags_off, &sv->reserved_bytes);
+    if (pool_bytes < sv->reserved_bytes) {
         delete sv;
         return set_error(MCLBM_ETOOSMALL, "pool smaller than mclbm_server_plan's reserved bytes");
     }
-    sv->heap.init(sv->table_bytes, pool_bytes - sv->table_bytes);
-    bool ok = hipHostMalloc(reinterpret_cast<void**>(&sv->host_table), sv->table_bytes, hipHostMallocDefault) ==
+    sv->heap.init(sv->reserved_bytes, pool_bytes - sv->reserved_bytes);
+    bool ok = hipHostMalloc(reinterpret_cast<void**>(&sv->host_table), sv->reserved_bytes, hipHostMallocDefault) ==
                   hipSuccess &&
+              hipHostMalloc(reinterpret_cast<void**>(&sv->host_flags), (size_t)cfg->max_active * sizeof(uint32_t),
+                            hipHostMallocDefault) == hipSuccess &&
               hipEventCreateWithFlags(&sv->round_done, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&sv->fork, hipEventDisableTiming) == hipSuccess;
     for (int g = 0; ok && g < kGroups; g++)  // default priority
@@ -224,7 +244,8 @@ MCLBM_EXPORT int mclbm_server_create(const mclbm_server_config* cfg, void* pool,
         mclbm_server_destroy(sv);
         return set_error(MCLBM_EHIP, "pinned staging, stream or event creation failed");
     }
-    std::memset(sv->host_table, 0, sv->table_bytes);
+    std::memset(sv->host_table, 0, sv->reserved_bytes);
+    std::memset(sv->host_flags, 0, (size_t)cfg->max_active * sizeof(uint32_t));
     *out = sv;
     return MCLBM_OK;
 }
@@ -240,7 +261,7 @@ MCLBM_EXPORT int mclbm_server_submit(mclbm_server* sv, const mclbm_params* p, co
         return set_error(MCLBM_EINVAL, "the server runs St. Venant-Kirchhoff and neo-Hooke materials");
     if (nsteps < 1) return set_error(MCLBM_EINVAL, "nsteps must be >= 1");
     bytes = align_up(bytes);
-    if (bytes > sv->pool_bytes - sv->table_bytes)
+    if (bytes > sv->pool_bytes - sv->reserved_bytes)
         return set_error(MCLBM_ETOOSMALL, "the request's arena exceeds the server's pool");
     for (int i = 0; i < 4; i++) {
         // validate the side programs now rather than at admission
@@ -274,7 +295,10 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
             advance(r.sim, r.round_steps);
             r.done_steps += r.round_steps;
             r.round_steps = 0;
-            if (r.done_steps < r.nsteps) {
+            // runs on unless it has all its steps or its displacement is no longer finite
+            const bool failed = r.slot >= 0 && sv->host_flags[r.slot] != 0;
+            r.slot = -1;
+            if (r.done_steps < r.nsteps && !failed) {
                 still.push_back(id);
                 continue;
             }
@@ -331,8 +355,19 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
             st->nitems += e.nstrip * e.nchunk;
         }
     }
+    // the failure scan of every simulation's displacement after the round; its
+    // flags go up as zeros with the tables
+    ScanEntry* scan = reinterpret_cast<ScanEntry*>(sv->host_table + sv->scan_off);
+    int nscan = 0;
+    for (int64_t id : sv->active) {
+        Request& r = sv->reqs[id];
+        r.slot = nscan;
+        scan_entry(r.sim, r.round_steps, nscan, &scan[nscan]);
+        nscan++;
+    }
+    std::memset(sv->host_table + sv->flags_off, 0, (size_t)nscan * sizeof(uint32_t));
     // 4. one upload, then the four groups' graphs side by side
-    SV_HIP(hipMemcpyAsync(sv->pool, sv->host_table, sv->table_bytes, hipMemcpyHostToDevice, sv->stream));
+    SV_HIP(hipMemcpyAsync(sv->pool, sv->host_table, sv->reserved_bytes, hipMemcpyHostToDevice, sv->stream));
     for (int g = 0; g < kGroups; g++)
         if (!sv->graph[g])
             if (int rc = capture(sv, g)) return rc;
@@ -343,6 +378,10 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
         SV_HIP(hipEventRecord(sv->join[g], sv->gstream[g]));
         SV_HIP(hipStreamWaitEvent(sv->stream, sv->join[g], 0));
     }
+    uint32_t* dflags = reinterpret_cast<uint32_t*>(sv->pool + sv->flags_off);
+    SV_HIP(launch_nanscan(reinterpret_cast<const ScanEntry*>(sv->pool + sv->scan_off), nscan, dflags, sv->stream));
+    SV_HIP(hipMemcpyAsync(sv->host_flags, dflags, (size_t)nscan * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          sv->stream));
     SV_HIP(hipEventRecord(sv->round_done, sv->stream));
     sv->in_flight = true;
     return MCLBM_OK;
@@ -354,6 +393,14 @@ MCLBM_EXPORT int mclbm_server_result(mclbm_server* sv, int64_t id, int32_t* stat
     if (it == sv->reqs.end()) return set_error(MCLBM_EINVAL, "unknown request id");
     *state = it->second.state;
     *status = it->second.status;
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_server_steps(mclbm_server* sv, int64_t id, int64_t* steps) {
+    if (!sv || !steps) return set_error(MCLBM_EINVAL, "NULL argument");
+    auto it = sv->reqs.find(id);
+    if (it == sv->reqs.end()) return set_error(MCLBM_EINVAL, "unknown request id");
+    *steps = it->second.done_steps;
     return MCLBM_OK;
 }
 
@@ -377,6 +424,7 @@ MCLBM_EXPORT int mclbm_server_destroy(mclbm_server* sv) {
     if (sv->fork) (void)hipEventDestroy(sv->fork);
     if (sv->round_done) (void)hipEventDestroy(sv->round_done);
     if (sv->host_table) (void)hipHostFree(sv->host_table);
+    if (sv->host_flags) (void)hipHostFree(sv->host_flags);
     delete sv;
     return MCLBM_OK;
 }

@@ -83,6 +83,7 @@ _sig = {
                                  C.POINTER(_i64)]),
     "mclbm_server_progress": (_i, [_vp, C.POINTER(_i64), C.c_int32, C.POINTER(C.c_int32)]),
     "mclbm_server_result": (_i, [_vp, _i64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "mclbm_server_steps": (_i, [_vp, _i64, C.POINTER(_i64)]),
     "mclbm_server_counts": (_i, [_vp, C.POINTER(_i64), C.POINTER(_i64), C.POINTER(_i64)]),
     "mclbm_server_destroy": (_i, [_vp]),
 }
@@ -221,6 +222,12 @@ def mclbm_server_counts(h: int):
     w, a, d = _i64(0), _i64(0), _i64(0)
     _check(_lib.mclbm_server_counts(_vp(h), C.byref(w), C.byref(a), C.byref(d)), "mclbm_server_counts")
     return w.value, a.value, d.value
+
+
+def mclbm_server_steps(h: int, rid: int) -> int:
+    n = _i64(0)
+    _check(_lib.mclbm_server_steps(_vp(h), int(rid), C.byref(n)), "mclbm_server_steps")
+    return n.value
 
 
 def mclbm_server_destroy(h: int) -> None:
@@ -394,6 +401,10 @@ class Server:
 
     def counts(self):
         return mclbm_server_counts(self._h)
+
+    def steps(self, rid) -> int:
+        """Steps the request has run (fewer than asked when it was stopped as unstable)."""
+        return mclbm_server_steps(self._h, rid)
 
     def drain(self):
         """Run turns until every submitted request is done; returns the finished ids in order."""

@@ -19,8 +19,10 @@ nu near 0; they are reported as unstable and left out of the latency figures.
 
   python -m paper_2502_00920_amd.serve [--requests 1000] [--seed 0]
       [--steps-min 1000] [--steps-max 20000] [--load 0.8] [--baseline 40]
-prints one JSON line: batched capacity, open-loop p50/p99 latency at the given
-fraction of that capacity, and the throughput of one-at-a-time FP64 solves.
+prints one JSON line: batched capacity (lattice updates run per second, and
+requests per second), open-loop p50/p99 latency with Poisson arrivals at the
+given fraction of that request rate, and the throughput of one-at-a-time FP64
+solves.
 """
 from __future__ import annotations
 
@@ -69,7 +71,9 @@ def _submit(server, r):
 
 
 def run_closed(reqs, precision="f32", **server_kw):
-    """Every request queued at once: the server's capacity in LUP/s."""
+    """Every request queued at once: the server's capacity in lattice updates
+    run per second (unstable requests stop early and count only the steps they
+    ran)."""
     import torch
     from . import mclbm
     sv = mclbm.Server(precision=precision, **server_kw)
@@ -78,9 +82,10 @@ def run_closed(reqs, precision="f32", **server_kw):
     sv.drain()
     dt = time.perf_counter() - t0
     res = {i: sv.result(rid) for i, rid in enumerate(ids)}
+    ran = sum(r["nx"] * r["ny"] * sv.steps(rid) for r, rid in zip(reqs, ids))
     del sv
     torch.cuda.empty_cache()
-    return lups(reqs) / dt, dt, res
+    return ran / dt, dt, res
 
 
 def run_open(reqs, rate, seed=1, precision="f32", **server_kw):
@@ -104,11 +109,12 @@ def run_open(reqs, rate, seed=1, precision="f32", **server_kw):
             time.sleep(max(0.0, min(arrival[nxt] - (time.perf_counter() - t0), 0.05)))
     total = time.perf_counter() - t0
     status = {i: sv.result(rid)[1] for rid, i in rid_of.items()}
+    ran = sum(reqs[i]["nx"] * reqs[i]["ny"] * sv.steps(rid) for rid, i in rid_of.items())
     del sv
     torch.cuda.empty_cache()
     lat = np.array([done_at[i] - arrival[i] for i in range(len(reqs)) if status[i] == 0])
     return {"requests": len(reqs), "rate_per_s": rate, "seconds": total,
-            "lups_per_s": lups(reqs) / total, "unstable": int(sum(1 for s in status.values() if s != 0)),
+            "lups_per_s": ran / total, "unstable": int(sum(1 for s in status.values() if s != 0)),
             "p50_s": float(np.percentile(lat, 50)) if lat.size else None,
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None}
 
@@ -138,8 +144,8 @@ def run_sequential(reqs, precision="f64"):
 def serving_report(n=1000, seed=0, steps=(1000, 20000), load=0.8, baseline=40, **server_kw):
     reqs = make_requests(n, seed=seed, steps=steps)
     cap, cap_s, res = run_closed(reqs, **server_kw)
-    mean_lup = lups(reqs) / len(reqs)
-    opn = run_open(reqs, rate=load * cap / mean_lup, **server_kw)
+    # Poisson arrivals at `load` times the closed loop's request rate
+    opn = run_open(reqs, rate=load * len(reqs) / cap_s, **server_kw)
     sub = reqs[:baseline]
     seq, seq_s, useq = run_sequential(sub, "f64")
     # accuracy of the batched FP32 results against the one-at-a-time FP64 ones
@@ -152,6 +158,7 @@ def serving_report(n=1000, seed=0, steps=(1000, 20000), load=0.8, baseline=40, *
     return {"workload": f"{n} requests, sides 64..1024, SVK/NH, nu 0..0.45, tension/shear/cantilever, "
                         f"{steps[0]}..{steps[1]} steps, seed {seed}",
             "batched_f32": {"capacity_lups_per_s": cap, "closed_loop_seconds": cap_s,
+                            "requests_per_s": len(reqs) / cap_s,
                             "unstable": int(sum(1 for v in res.values() if v[1] != 0))},
             "open_loop_f32": opn,
             "sequential_f64": {"lups_per_s": seq, "requests": len(sub), "seconds": seq_s},

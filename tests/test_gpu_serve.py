@@ -8,7 +8,8 @@
   can differ in the last bit);
 - admission by memory: a pool with room for two arenas serves a longer queue;
 - the server's FP64 results against the oracle;
-- a diverging request is reported as unstable and does not disturb the rest.
+- a diverging request is reported as unstable, stops early, and does not disturb
+  the rest.
 """
 import os
 
@@ -168,7 +169,11 @@ def test_unstable_request_is_flagged(M):
     s.step(3000)
     diverged = s.diag()["nonfinite"]
     assert sv.result(bid)[1] == (M.MCLBM_EUNSTABLE if diverged else M.MCLBM_OK)
+    if diverged:  # the failure scan stops it early, at a round boundary
+        ran = sv.steps(bid)
+        print("diverging request stopped after", ran, "of 3000 steps", flush=True)
+        assert ran < 3000 and ran % 32 == 0
     for r, rid in zip(good, gids):
         state, status, u = sv.result(rid)
-        assert state == 2 and status == 0
+        assert state == 2 and status == 0 and sv.steps(rid) == r["nsteps"]
         assert close(u, alone_via_sim(M, r, "f32"), "f32")
