@@ -24,6 +24,9 @@ FLAGS = [
 ]
 
 
+DEMO = os.path.join(PKG, "mclbm_demo")
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, "-x", "hip", *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
@@ -31,7 +34,20 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_demo(verbose)
     return LIB
+
+
+def build_demo(verbose: bool = False) -> str:
+    """The stand-alone C++ user of the ABI (host code only, linked to libmclbm.so)."""
+    tmp = DEMO + ".tmp"
+    cmd = [HIPCC, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"), os.path.join(CSRC, "mclbm_demo.cpp"),
+           "-L", PKG, "-lmclbm", "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, DEMO)
+    return DEMO
 
 
 if __name__ == "__main__":
