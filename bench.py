@@ -273,6 +273,36 @@ def config_table() -> dict:
     return out
 
 
+def error_growth(steps: int = 20000, every: int = 2000) -> dict:
+    """Long-run error of each storage format against FP64 storage on the
+    cantilever workload (2048x128 neo-Hooke, Gaussian traction pulse): the
+    relative L2 of u every `every` steps, all modes advanced in lockstep on the
+    GPU (the oracle would take hours for this run)."""
+    import numpy as np
+    import torch
+    from paper_2502_00920_amd import mclbm
+    from paper_2502_00920_amd import workloads as W
+
+    w = W.beam2048()
+    sims = {m: mclbm.sim_from_workload(w, precision=m) for m in ("f64", "f32", "f16", "bf16")}
+    for s in sims.values():
+        s.init()
+    hist = []
+    for n in range(every, steps + 1, every):
+        for s in sims.values():
+            s.step(every)
+        ref = sims["f64"].read("u")
+        row = {"step": n, "max_u_f64": float(np.abs(ref).max())}
+        for m in ("f32", "f16", "bf16"):
+            u = sims[m].read("u")
+            row[m] = float(np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300))
+        print("# " + json.dumps(row), file=sys.stderr, flush=True)
+        hist.append(row)
+    del sims
+    torch.cuda.empty_cache()
+    return {"workload": f"{w.name}, FP64 storage as the reference", "history": hist}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -282,6 +312,8 @@ def main():
     ap.add_argument("--mode", choices=["all", "f32", "f64", "f16", "bf16"], default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--error-growth", action="store_true",
+                    help="print the long-run error of each storage format against FP64 as one JSON line and exit")
     ap.add_argument("--configs", action="store_true",
                     help="print the per-configuration rates (GPU and CPU oracle) as one JSON line and exit")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -302,6 +334,9 @@ def main():
 
     if args.configs:
         print(json.dumps(config_table()), flush=True)
+        return
+    if args.error_growth:
+        print(json.dumps(error_growth()), flush=True)
         return
 
     modes = ["f32", "f64", "f16", "bf16"] if args.mode == "all" else [args.mode]
