@@ -193,6 +193,16 @@ int mclbm_step(mclbm_sim* s, int64_t nsteps);
  * stream.  For measurement; the results equal those of mclbm_step bitwise. */
 int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step);
 
+/* Advance nsteps as mclbm_step does, in runs of `every` (>= 1) steps, and after
+ * each run scan the displacement for values that are not finite (the failure
+ * modes the paper names: the CFL limit and large-strain instability, Sect. 3.2
+ * and Sect. 4).  Stops at the first run that leaves one and returns
+ * MCLBM_EUNSTABLE; *steps_run (may be NULL) receives the steps taken by this
+ * call either way.  Synchronises the stream after every run.  Uses the
+ * arena's diagnostics result area, so it must not overlap a mclbm_diag on
+ * another stream.  Results equal those of mclbm_step bitwise. */
+int mclbm_step_checked(mclbm_sim* s, int64_t nsteps, int64_t every, int64_t* steps_run);
+
 /* Plain device copy of nbytes (a multiple of 4, buffers 4-byte aligned) from
  * src to dst, enqueued on stream (a hipStream_t; NULL = null stream).  Not
  * part of the method: the reference kernel of known traffic against which the

@@ -3,7 +3,9 @@
 // caller provides the arena and the stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -347,6 +349,37 @@ MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
         HIP_TRY(launch_step(s->p.precision, s->p.material, step_args(s), s->stream));
         s->cur = 1 - s->cur;
         s->n++;
+    }
+    return MCLBM_OK;
+}
+
+MCLBM_EXPORT int mclbm_step_checked(mclbm_sim* s, int64_t nsteps, int64_t every, int64_t* steps_run) {
+    if (steps_run) *steps_run = 0;
+    if (int e = check_steppable(s, nsteps)) return e;
+    if (every < 1) return fail(MCLBM_EINVAL, "every must be >= 1");
+    // the scan's table entry and its flag sit in the arena's diagnostics result area
+    char* area = static_cast<char*>(at(s, s->L.off_out));
+    static_assert(sizeof(ScanEntry) + sizeof(uint32_t) <= 8 * sizeof(double), "result area too small");
+    int64_t done = 0;
+    while (done < nsteps) {
+        const int64_t k = std::min<int64_t>(every, nsteps - done);
+        if (int rc = mclbm_step(s, k)) return rc;
+        done += k;
+        struct {
+            ScanEntry e;
+            uint32_t flag;
+        } h;
+        std::memset(&h, 0, sizeof h);
+        scan_entry(s, 0, 0, &h.e);
+        uint32_t flag = 0;
+        HIP_TRY(hipMemcpyAsync(area, &h, sizeof h, hipMemcpyHostToDevice, s->stream));
+        HIP_TRY(launch_nanscan(reinterpret_cast<const ScanEntry*>(area), 1,
+                               reinterpret_cast<uint32_t*>(area + offsetof(decltype(h), flag)), s->stream));
+        HIP_TRY(hipMemcpyAsync(&flag, area + offsetof(decltype(h), flag), sizeof flag, hipMemcpyDeviceToHost,
+                               s->stream));
+        HIP_TRY(hipStreamSynchronize(s->stream));
+        if (steps_run) *steps_run = done;
+        if (flag) return fail(MCLBM_EUNSTABLE, "displacement not finite by step %lld", (long long)s->n);
     }
     return MCLBM_OK;
 }

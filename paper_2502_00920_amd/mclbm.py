@@ -67,6 +67,7 @@ _sig = {
     "mclbm_init": (_i, [_vp, _vp, _vp, _i]),
     "mclbm_step": (_i, [_vp, _i64]),
     "mclbm_step_timed": (_i, [_vp, _i64, C.POINTER(C.c_double)]),
+    "mclbm_step_checked": (_i, [_vp, _i64, _i64, C.POINTER(_i64)]),
     "mclbm_copy": (_i, [_vp, _vp, _sz, _vp]),
     "mclbm_stepno": (_i64, [_vp]),
     "mclbm_field_components": (_i, [_i]),
@@ -134,6 +135,17 @@ def mclbm_init(h: int, u0_ptr: Optional[int], j0_ptr: Optional[int], on_device: 
 
 def mclbm_step(h: int, nsteps: int) -> None:
     _check(_lib.mclbm_step(_vp(h), int(nsteps)), "mclbm_step")
+
+
+def mclbm_step_checked(h: int, nsteps: int, every: int):
+    """(finite, steps run): nsteps in runs of `every`, stopped at the first run
+    that leaves a displacement that is not finite."""
+    done = _i64(0)
+    rc = _lib.mclbm_step_checked(_vp(h), int(nsteps), int(every), C.byref(done))
+    if rc == MCLBM_EUNSTABLE:
+        return False, done.value
+    _check(rc, "mclbm_step_checked")
+    return True, done.value
 
 
 def mclbm_step_timed(h: int, nsteps: int) -> float:
@@ -310,6 +322,11 @@ class Sim:
 
     def step(self, n: int = 1):
         mclbm_step(self._h, n)
+
+    def step_checked(self, n: int, every: int = 100):
+        """Advance n steps, checking the displacement every `every` steps; returns
+        (finite, steps run)."""
+        return mclbm_step_checked(self._h, n, every)
 
     def step_timed(self, n: int) -> float:
         """Advance n steps; returns the mean ms of one step launch."""

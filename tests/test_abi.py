@@ -110,6 +110,9 @@ def test_host_side_errors_without_gpu(M):
             M.mclbm_step_timed(h, 1)
         assert e.value.code == M.MCLBM_ESTATE
         with pytest.raises(M.MclbmError) as e:
+            M.mclbm_step_checked(h, 10, 5)
+        assert e.value.code == M.MCLBM_ESTATE
+        with pytest.raises(M.MclbmError) as e:
             M.mclbm_read(h, 0, fake, 1)
         assert e.value.code == M.MCLBM_ESTATE
         with pytest.raises(M.MclbmError) as e:

@@ -445,6 +445,30 @@ def test_diag_parity(M):
     assert d["max_u"] == pytest.approx(od["max_u"], rel=1e-12)
 
 
+def test_step_checked(M):
+    """Checked steps equal plain steps bitwise on a finite run, and stop a
+    diverging one at the first check after it goes non-finite."""
+    print_case("checked steps")
+    nx, ny = 77, 45
+    a = M.Sim(nx, ny, mu=0.05, nu=0.2, tau=0.55, material="svk")
+    b = M.Sim(nx, ny, mu=0.05, nu=0.2, tau=0.55, material="svk")
+    for s in (a, b):
+        for side, spec in walls("DNNN").items():
+            s.set_side(side, *((spec,) if isinstance(spec, str) else tuple(spec)))
+        s.init(W.smooth_field(nx, ny, 0.04, 2))
+    a.step(250)
+    ok, ran = b.step_checked(250, every=60)
+    assert ok and ran == 250 and b.diag()["step"] == 250
+    assert np.array_equal(a.read("u"), b.read("u"))
+    s = M.Sim(32, 32, mu=0.05, nu=0.49, tau=0.55, material="svk")  # beyond the bulk bound 5/11
+    for side in W.SIDES:
+        s.set_side(side, "periodic")
+    s.init(W.random_field(32, 32, 1e-3, 1))
+    ok, ran = s.step_checked(3000, every=100)
+    print("diverging run stopped after", ran, "steps", flush=True)
+    assert not ok and ran < 3000 and ran % 100 == 0 and s.diag()["nonfinite"]
+
+
 def test_diag_flags_nonfinite(M):
     print_case("diagnostics flag a diverging run")
     s = M.Sim(32, 32, mu=0.05, nu=0.45, tau=0.55, material="linear")
