@@ -1066,10 +1066,21 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 
 // ---- launchers ---------------------------------------------------------------------------------
 
+// Waves per launch of march_kernel to aim for, by population storage.  Longer
+// chunks prime fewer rows, more waves balance the tail.  On the 8192^2 lattice
+// (2048 resident waves):
+//   FP32: 16384 waves (64-row chunks) gave 47.3k MLUPS; 12288 / 20480 / 24576 / 32768
+//         gave 4 %, 1 %, 4 % and 2 % less;
+//   FP64: 49152 (22 rows) gave 26.9k; 16384 gave 3.5 % less, 32768 and 65536 0.5 %;
+//   FP16, BF16: 32768 (34 rows) gave 69.1k / 69.5k; 16384 and 49152 gave 1 % less.
+template <int PR>
+constexpr long march_waves() {
+    return PR == PREC_F64 ? 49152 : PR == PREC_F32 ? 16384 : 32768;
+}
+
 // rows per chunk of march_kernel: a multiple of its iterations per loop trip
-// minus the two priming rows, with enough waves to fill the chip twice over
-static int march_chunk(const Geometry& g, int nstrip, int L) {
-    const long target = 16384;
+// minus the two priming rows, with about `target` work items in all
+static int march_chunk(const Geometry& g, int nstrip, int L, long target) {
     long c = ((long)g.ny * nstrip + target - 1) / target;
     long m = (c + 2 + L - 1) / L;
     if (m < 1) m = 1;
@@ -1081,7 +1092,7 @@ template <int PR, int MAT, int HR, int D>
 static void launch_march(const StepArgs& a, hipStream_t st) {
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);
     const int nstrip = a.g.pitch / 64;
-    const int chunk = march_chunk(a.g, nstrip, L);
+    const int chunk = march_chunk(a.g, nstrip, L, march_waves<PR>());
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
     hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
                        nstrip, nchunk, chunk);
