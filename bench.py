@@ -135,6 +135,18 @@ def copy_gbs(nbytes: int = COPY_BYTES) -> dict:
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(n: int = 1024, steps: int = 1000):
     """The FP64 CPU oracle on the host's cores over the n x n subrun of the
     benchmark workload (all its steps).  Returns the baseline record and the
@@ -156,7 +168,7 @@ def cpu_baseline(n: int = 1024, steps: int = 1000):
     dt = time.perf_counter() - t0
     rec = {"value": w.nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
            "sample": f"FP64 oracle, {n}x{n} subrun of the SVK tension workload, all {steps} steps, "
-                     f"{dt:.1f} s, {threads} OpenMP threads on {platform.processor() or platform.machine()}"}
+                     f"{dt:.1f} s, {threads} OpenMP threads on {cpu_model()}"}
     return rec, o.read("u"), o.read("p")
 
 
@@ -248,7 +260,7 @@ def config_table() -> dict:
             (W.shear128(0.25), ("f64", "f32"), 2000, 200),
             (W.beam2048(), ("f64", "f32", "f16"), 2000, 100),
             (W.tension_large(1024, 1000), ("f64", "f32", "f16"), 1000, 100)]
-    out = {"host_threads": threads, "rows": []}
+    out = {"host_threads": threads, "cpu": cpu_model(), "rows": []}
     for w, modes, gsteps, osteps in cfgs:
         row = {"workload": w.name, "nodes": w.nx * w.ny}
         for m in modes:
@@ -258,6 +270,13 @@ def config_table() -> dict:
             torch.cuda.synchronize()
             ms = s.step_timed(gsteps)
             row[f"gpu_{m}_mlups"] = w.nx * w.ny / ms / 1e3
+            # the same steps launched back to back, events around the whole run
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(gsteps)
+            e1.record()
+            e1.synchronize()
+            row[f"gpu_{m}_async_mlups"] = w.nx * w.ny * gsteps / e0.elapsed_time(e1) / 1e3
             del s
         torch.cuda.empty_cache()
         for t in (1, threads):

@@ -788,9 +788,13 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
     }
 }
 
-// The step of one lattice: one work item per wave.
+// The step of one lattice: one work item per wave.  Two waves per SIMD, but one
+// in FP64: its loop needs about 306 registers, and at two waves (256 each) the
+// 50 spilled to scratch cost more than the halved occupancy (8192^2 tension:
+// 26.9k MLUPS at two waves, 28.4k at one).
 template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, 2) void march_kernel(StepArgs a, int nstrip, int nchunk, int chunk) {
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(StepArgs a, int nstrip, int nchunk,
+                                                                             int chunk) {
     __shared__ HaloOf<PR, HR> halo_lds[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1067,15 +1071,15 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 // ---- launchers ---------------------------------------------------------------------------------
 
 // Waves per launch of march_kernel to aim for, by population storage.  Longer
-// chunks prime fewer rows, more waves balance the tail.  On the 8192^2 lattice
-// (2048 resident waves):
-//   FP32: 16384 waves (64-row chunks) gave 47.3k MLUPS; 12288 / 20480 / 24576 / 32768
-//         gave 4 %, 1 %, 4 % and 2 % less;
-//   FP64: 49152 (22 rows) gave 26.9k; 16384 gave 3.5 % less, 32768 and 65536 0.5 %;
+// chunks prime fewer rows, more waves balance the tail.  On the 8192^2 lattice:
+//   FP32 (2048 resident waves): 16384 waves (64-row chunks) gave 47.3k MLUPS;
+//         12288 / 20480 / 24576 / 32768 gave 4 %, 1 %, 4 % and 2 % less;
+//   FP64 (1024 resident waves): 32768 (34 rows) gave 28.4k; 12288 / 16384 / 24576 /
+//         49152 / 65536 gave 4 %, 3 %, 1.5 %, 1 % and 3 % less;
 //   FP16, BF16: 32768 (34 rows) gave 69.1k / 69.5k; 16384 and 49152 gave 1 % less.
 template <int PR>
 constexpr long march_waves() {
-    return PR == PREC_F64 ? 49152 : PR == PREC_F32 ? 16384 : 32768;
+    return PR == PREC_F32 ? 16384 : 32768;
 }
 
 // rows per chunk of march_kernel: a multiple of its iterations per loop trip
