@@ -809,11 +809,15 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
 // items 4b..4b+3, then the same plus four times the grid, so that neighbouring
 // strips run on one CU and share their halo lines in its L2.  An item's work
 // depends only on its own lattice, so a simulation's results do not depend on
-// its company.
-constexpr int kBatchBlocks = 512;  // two blocks of four waves per CU
+// its company.  FP64 runs one wave per SIMD, as in march_kernel (no spills; on
+// the serving mix 20.8 against 16.2 GLUPS at two waves), so one block per CU.
+template <int PR>
+constexpr int batch_blocks() {
+    return PR == PREC_F64 ? 256 : 512;  // blocks of four waves: one or two per CU
+}
 
 template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
     __shared__ HaloOf<PR, HR> halo_lds[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1115,11 +1119,13 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
 }
 
 hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st) {
-    const dim3 grid(kBatchBlocks), block(256);
+    const dim3 block(256);
     if (prec == PREC_F64) {
+        const dim3 grid(batch_blocks<PREC_F64>());
         if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         else hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_NH, 6, 2>), grid, block, 0, st, step);
     } else {
+        const dim3 grid(batch_blocks<PREC_F32>());
         if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         else hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_NH, 6, 2>), grid, block, 0, st, step);
     }
