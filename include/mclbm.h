@@ -46,7 +46,7 @@ enum mclbm_status {
     MCLBM_EINVAL = -1,    /* invalid argument or parameter                      */
     MCLBM_ETOOSMALL = -2, /* arena smaller than mclbm_plan reported             */
     MCLBM_EHIP = -3,      /* a HIP runtime call failed (message has the detail) */
-    MCLBM_EUNSTABLE = -4, /* non-finite values found by mclbm_diag              */
+    MCLBM_EUNSTABLE = -4, /* non-finite values, or growth past growth_limit     */
     MCLBM_ESTATE = -5     /* call out of order (e.g. step before init)          */
 };
 
@@ -132,6 +132,13 @@ typedef struct {
                            * (n_q - n_qbar)/2, relaxed at 1/tau as in BGK, and
                            * its even part (n_q + n_qbar)/2, relaxed at
                            * 1/tau_plus.  tau_plus = tau is BGK.                */
+    double growth_limit;  /* 0: off.  > 0: a displacement |u| above it at any
+                           * node counts as growth, the sign of a run that has
+                           * left the regime the scheme is stable in (Sect. 3.2
+                           * bounds nu for stability; beyond it runs diverge):
+                           * mclbm_diag sets growth and returns EUNSTABLE, and
+                           * mclbm_step_checked stops, like for a non-finite
+                           * value.  In units of length, like dx.               */
 } mclbm_params;
 
 typedef struct {
@@ -147,6 +154,7 @@ typedef struct {
     double ekin;          /* sum_X |j|^2 / (2 rho0), j as MCLBM_FIELD_J          */
     double max_u;         /* max_X |u_n|                                        */
     int32_t nonfinite;    /* 1 when any u or j is NaN or infinite               */
+    int32_t growth;       /* 1 when growth_limit > 0 and max_u exceeds it       */
     int32_t cfl_excess;   /* 1 when the dilatational wave speed exceeds the
                            * lattice speed, c_d > c, i.e. nu > 1/4: beyond the
                            * CFL bound of first-order boundary stencils
@@ -194,9 +202,10 @@ int mclbm_step(mclbm_sim* s, int64_t nsteps);
 int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step);
 
 /* Advance nsteps as mclbm_step does, in runs of `every` (>= 1) steps, and after
- * each run scan the displacement for values that are not finite (the failure
- * modes the paper names: the CFL limit and large-strain instability, Sect. 3.2
- * and Sect. 4).  Stops at the first run that leaves one and returns
+ * each run scan the displacement for values that are not finite or, with a
+ * growth_limit, for |u| above it (the failure modes the paper names: the CFL
+ * limit and large-strain instability, Sect. 3.2 and Sect. 4).  Stops at the
+ * first run that leaves one and returns
  * MCLBM_EUNSTABLE; *steps_run (may be NULL) receives the steps taken by this
  * call either way.  Synchronises the stream after every run.  Uses the
  * arena's diagnostics result area, so it must not overlap a mclbm_diag on
@@ -221,7 +230,8 @@ int mclbm_field_components(int field);
 int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device);
 
 /* Global diagnostics at t_n (deterministic reductions on the device).
- * Returns EUNSTABLE (with *out filled) when u or j hold non-finite values. */
+ * Returns EUNSTABLE (with *out filled) when u or j hold non-finite values or
+ * max_u exceeds the growth_limit. */
 int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out);
 
 /* Checkpoints: the bytes of the state (populations, displacement, step
@@ -254,7 +264,8 @@ const char* mclbm_last_error(void);
  * caller's buffer) and admits waiting requests in arrival order while a slot
  * is free and their arena (mclbm_plan bytes) fits in the caller's pool.
  * After every round a scan of each active simulation's displacement flags the
- * ones that are no longer finite; they finish at the next turn as
+ * ones that are no longer finite or have passed their growth_limit; they
+ * finish at the next turn as
  * MCLBM_EUNSTABLE instead of running out their steps (the instabilities of
  * Sect. 3.2 and Sect. 4: CFL excess, large strain).
  *
@@ -299,7 +310,7 @@ int mclbm_server_submit(mclbm_server* sv, const mclbm_params* p, const mclbm_sid
 int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int32_t cap, int32_t* ndone);
 
 /* State (enum mclbm_request_state) and status of a request: MCLBM_OK, or
- * MCLBM_EUNSTABLE when its final state holds non-finite values, or the error
+ * MCLBM_EUNSTABLE when the failure scan flagged it, or the error
  * that stopped it. */
 int mclbm_server_result(mclbm_server* sv, int64_t id, int32_t* state, int32_t* status);
 

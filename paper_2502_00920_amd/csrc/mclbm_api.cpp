@@ -96,6 +96,8 @@ int check_params(const mclbm_params* p) {
     if (!(p->tau > 0.5)) return fail(MCLBM_EINVAL, "tau must exceed 0.5 (got %g)", p->tau);
     if (!(p->tau_plus == 0.0 || p->tau_plus > 0.5))
         return fail(MCLBM_EINVAL, "tau_plus must be 0 (BGK) or exceed 0.5 (got %g)", p->tau_plus);
+    if (!(p->growth_limit >= 0.0 && std::isfinite(p->growth_limit)))
+        return fail(MCLBM_EINVAL, "growth_limit must be finite and >= 0 (got %g)", p->growth_limit);
     if (!(p->nu > -1.0 && p->nu < 0.5)) return fail(MCLBM_EINVAL, "nu must lie in (-1, 0.5) (got %g)", p->nu);
     if (p->material < MCLBM_SVK || p->material > MCLBM_LINEAR)
         return fail(MCLBM_EINVAL, "unknown material %d", p->material);
@@ -459,6 +461,7 @@ void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e) {
     const int c = (s->cur + (int)(k & 1)) & 1;
     e->u = static_cast<const double*>(at(s, s->L.off_u[c]));
     e->plane = s->g.plane;
+    e->limit2 = s->p.growth_limit * s->p.growth_limit;
     e->nx = s->g.nx;
     e->ny = s->g.ny;
     e->pitch = s->g.pitch;
@@ -534,9 +537,13 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
     out->ekin = h[2];
     out->max_u = std::sqrt(h[3]);
     out->nonfinite = h[4] != 0.0;
+    out->growth = s->p.growth_limit > 0.0 && out->max_u > s->p.growth_limit;
     // c_d^2 = (lambda + 2 mu) / rho0 against c^2 = 3 mu / rho0
     out->cfl_excess = 2.0 * s->p.mu * s->p.nu / (1.0 - 2.0 * s->p.nu) > s->p.mu;
     if (out->nonfinite) return fail(MCLBM_EUNSTABLE, "non-finite u or j at step %lld", (long long)s->n);
+    if (out->growth)
+        return fail(MCLBM_EUNSTABLE, "max |u| %g above the growth limit %g at step %lld", out->max_u,
+                    s->p.growth_limit, (long long)s->n);
     return MCLBM_OK;
 }
 

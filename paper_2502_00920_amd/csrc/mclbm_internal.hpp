@@ -66,11 +66,13 @@ inline size_t batch_step_bytes(int max_sims) {
     return (sizeof(BatchStep) + (size_t)(max_sims - 1) * sizeof(BatchEntry) + 255) / 256 * 256;
 }
 
-// One lattice's displacement for the batching server's failure scan: u at
-// [2][ny][pitch]; the scan raises flags[slot] if any u of a node is not finite.
+// One lattice's displacement for the failure scan: u at [2][ny][pitch]; the
+// scan raises flags[slot] if any u of a node is not finite or, when limit2 > 0,
+// if |u|^2 exceeds limit2.
 struct ScanEntry {
     const double* u;
     long long plane;
+    double limit2;
     int nx, ny, pitch, slot;
 };
 // scan n entries (a table in device memory) into flags (device memory, cleared

@@ -1042,10 +1042,10 @@ __global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int n
     if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
-// Failure scan of the batching server: every node of every listed lattice, both
-// displacement components; a wave that sees a value that is not finite raises its
-// lattice's flag with one lane's buffer store (a vector store: no scalar-cache
-// writes; concurrent stores all write 1).
+// Failure scan: every node of every listed lattice, both displacement components;
+// a wave that sees a value that is not finite, or a |u| above the entry's growth
+// limit, raises its lattice's flag with one lane's buffer store (a vector store:
+// no scalar-cache writes; concurrent stores all write 1).
 constexpr int kScanBlocks = 1024;
 
 __global__ __launch_bounds__(256) void nanscan_kernel(const ScanEntry* __restrict__ tab, int n,
@@ -1058,7 +1058,8 @@ __global__ __launch_bounds__(256) void nanscan_kernel(const ScanEntry* __restric
         bool bad = false;
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nodes; i += nthreads) {
             const size_t o = (size_t)(i / nx) * (size_t)s.pitch + i % nx;
-            bad |= !isfinite(s.u[o]) || !isfinite(s.u[(size_t)s.plane + o]);
+            const double ux = s.u[o], uy = s.u[(size_t)s.plane + o];
+            bad |= !isfinite(ux) || !isfinite(uy) || (s.limit2 > 0.0 && ux * ux + uy * uy > s.limit2);
         }
         const uint64_t any = __builtin_amdgcn_ballot_w64(bad);
         if (any && lane == (int)__builtin_ctzll(any))

@@ -42,7 +42,8 @@ class mclbm_params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("material", C.c_int32),
                 ("precision", C.c_int32), ("dx", C.c_double), ("rho0", C.c_double),
                 ("mu", C.c_double), ("nu", C.c_double), ("tau", C.c_double),
-                ("body", C.c_double * 2), ("tau_plus", C.c_double)]
+                ("body", C.c_double * 2), ("tau_plus", C.c_double),
+                ("growth_limit", C.c_double)]
 
 
 class mclbm_side_spec(C.Structure):
@@ -56,7 +57,8 @@ class mclbm_server_config(C.Structure):
 
 class mclbm_diag_out(C.Structure):
     _fields_ = [("step", C.c_int64), ("momentum", C.c_double * 2), ("ekin", C.c_double),
-                ("max_u", C.c_double), ("nonfinite", C.c_int32), ("cfl_excess", C.c_int32)]
+                ("max_u", C.c_double), ("nonfinite", C.c_int32), ("growth", C.c_int32),
+                ("cfl_excess", C.c_int32)]
 
 
 _vp, _i, _i64, _sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
@@ -138,8 +140,8 @@ def mclbm_step(h: int, nsteps: int) -> None:
 
 
 def mclbm_step_checked(h: int, nsteps: int, every: int):
-    """(finite, steps run): nsteps in runs of `every`, stopped at the first run
-    that leaves a displacement that is not finite."""
+    """(ok, steps run): nsteps in runs of `every`, stopped at the first run
+    that leaves a displacement that is not finite or, with a growth limit, above it."""
     done = _i64(0)
     rc = _lib.mclbm_step_checked(_vp(h), int(nsteps), int(every), C.byref(done))
     if rc == MCLBM_EUNSTABLE:
@@ -249,13 +251,14 @@ def mclbm_server_destroy(h: int) -> None:
 # ---- convenience wrapper (torch owns the device memory and the stream) -------------------------
 
 def make_params(nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0, dx=1.0,
-                body=(0.0, 0.0), tau_plus=0.0) -> mclbm_params:
+                body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0) -> mclbm_params:
     p = mclbm_params()
     p.nx, p.ny = int(nx), int(ny)
     p.material, p.precision = MATERIAL[material], PRECISION[precision]
     p.dx, p.rho0, p.mu, p.nu, p.tau = float(dx), float(rho0), float(mu), float(nu), float(tau)
     p.body[0], p.body[1] = float(body[0]), float(body[1])
     p.tau_plus = float(tau_plus or 0.0)
+    p.growth_limit = float(growth_limit or 0.0)
     return p
 
 
@@ -272,12 +275,13 @@ class Sim:
     [comp, ny, nx] on the device (or numpy arrays with ``host=True``)."""
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0,
-                 dx=1.0, body=(0.0, 0.0), tau_plus=0.0, device="cuda", stream=None):
+                 dx=1.0, body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0, device="cuda", stream=None):
         import torch
         self.torch = torch
         self.nx, self.ny = int(nx), int(ny)
         self.params = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material,
-                                  precision=precision, rho0=rho0, dx=dx, body=body, tau_plus=tau_plus)
+                                  precision=precision, rho0=rho0, dx=dx, body=body, tau_plus=tau_plus,
+                                  growth_limit=growth_limit)
         self.arena_bytes, self.dt = mclbm_plan(self.params)
         self.device = torch.device(device)
         self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
@@ -325,7 +329,8 @@ class Sim:
 
     def step_checked(self, n: int, every: int = 100):
         """Advance n steps, checking the displacement every `every` steps; returns
-        (finite, steps run)."""
+        (ok, steps run), ok False when a check found a value that is not finite
+        or a |u| above the growth limit."""
         return mclbm_step_checked(self._h, n, every)
 
     def step_timed(self, n: int) -> float:
@@ -342,7 +347,7 @@ class Sim:
         d = mclbm_diag(self._h)
         return {"step": d.step, "momentum": np.array([d.momentum[0], d.momentum[1]]),
                 "ekin": d.ekin, "max_u": d.max_u, "nonfinite": bool(d.nonfinite),
-                "cfl_excess": bool(d.cfl_excess)}
+                "growth": bool(d.growth), "cfl_excess": bool(d.cfl_excess)}
 
     def save(self):
         buf = self.torch.empty(mclbm_state_bytes(self._h), dtype=self.torch.uint8, device=self.device)
@@ -393,10 +398,10 @@ class Server:
                 pass
 
     def submit(self, nx, ny, *, mu, nu, tau, material, sides, nsteps, u0=None, rho0=1.0, dx=1.0,
-               body=(0.0, 0.0), tau_plus=0.0) -> int:
+               body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0) -> int:
         """sides: {"left": (bc, kind, amp, t0, t1, width) or bc, ...}; missing sides are free."""
         p = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=self.precision,
-                        rho0=rho0, dx=dx, body=body, tau_plus=tau_plus)
+                        rho0=rho0, dx=dx, body=body, tau_plus=tau_plus, growth_limit=growth_limit)
         specs = []
         for name in ("left", "right", "bottom", "top"):
             spec = sides.get(name, "neumann")

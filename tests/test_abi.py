@@ -54,7 +54,8 @@ def test_plan_validation(M):
     assert nbytes > 2 * 9 * 32 * 64 * 8
     bad = [dict(nx=2), dict(ny=1), dict(tau=0.5), dict(nu=0.5), dict(nu=-1.0), dict(mu=0.0),
            dict(rho0=-1.0), dict(dx=0.0), dict(tau_plus=0.5), dict(tau_plus=-1.0),
-           dict(tau_plus=float("nan"))]
+           dict(tau_plus=float("nan")), dict(growth_limit=-1.0), dict(growth_limit=float("inf")),
+           dict(growth_limit=float("nan"))]
     for b in bad:
         kw = dict(nx=32, ny=32, mu=0.05, nu=0.3, tau=1.0)
         kw.update(b)
@@ -63,6 +64,7 @@ def test_plan_validation(M):
             M.mclbm_plan(M.make_params(nx, ny, **kw))
         assert e.value.code == M.MCLBM_EINVAL
     M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, tau_plus=0.8))  # the option is accepted
+    M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, growth_limit=2.5))
     p = M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0)
     p.material = 7
     with pytest.raises(M.MclbmError):

@@ -469,6 +469,34 @@ def test_step_checked(M):
     assert not ok and ran < 3000 and ran % 100 == 0 and s.diag()["nonfinite"]
 
 
+def test_growth_limit(M):
+    """A growth limit on |u|: checked steps stop at the first check whose
+    maximum displacement (as the diagnostics report it on an unlimited twin run)
+    exceeds the limit, and the diagnostics flag it."""
+    print_case("growth limit")
+    w = W.tension32()
+    limit, every = 0.5, 20
+    a = M.sim_from_workload(w, precision="f64", growth_limit=limit)
+    b = M.sim_from_workload(w, precision="f64")
+    for s in (a, b):
+        s.init()
+    ok, ran = a.step_checked(2000, every=every)
+    crossed = None
+    for k in range(every, 2000 + every, every):
+        b.step(every)
+        if b.diag()["max_u"] > limit:
+            crossed = k
+            break
+    print("limit", limit, "stopped after", ran, "steps; max |u| passed it at", crossed, flush=True)
+    assert crossed is not None and not ok and ran == crossed
+    assert np.array_equal(a.read("u"), b.read("u"))
+    out = M.mclbm_diag_out()
+    assert M._lib.mclbm_diag(M.C.c_void_p(a._h), M.C.byref(out)) == M.MCLBM_EUNSTABLE and out.growth
+    d = a.diag()
+    assert d["growth"] and not d["nonfinite"] and d["max_u"] > limit
+    assert not b.diag()["growth"]
+
+
 def test_diag_flags_nonfinite(M):
     print_case("diagnostics flag a diverging run")
     s = M.Sim(32, 32, mu=0.05, nu=0.45, tau=0.55, material="linear")

@@ -18,6 +18,7 @@ import pytest
 
 import oracle
 from paper_2502_00920_amd import serve as S
+from paper_2502_00920_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
@@ -149,6 +150,32 @@ def test_server_two_relaxation_times(M):
         e = np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)
         print(r["case"], r["nx"], r["material"], r["tau_plus"], f"{e:.2e}", flush=True)
         assert e <= 1e-12
+
+
+def test_growth_limit_stops_a_request(M):
+    """A request with a growth limit below the displacement its load reaches
+    stops at the first round boundary past it; its neighbours run out."""
+    print("\n[case] server stops a request at its growth limit", flush=True)
+    w = W.tension32()
+    sides = {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()}
+    good = small_requests(2, seed=5)
+    sv = M.Server(precision="f64", steps_per_round=16, max_active=4, pool_bytes=64 << 20)
+    lid = sv.submit(w.nx, w.ny, mu=w.mu, nu=w.nu, tau=w.tau, material=w.material, sides=sides,
+                    nsteps=1000, growth_limit=0.5)
+    gids = [S._submit(sv, r) for r in good]
+    sv.drain()
+    state, status, u = sv.result(lid)
+    ran = sv.steps(lid)
+    print("request stopped after", ran, "steps", flush=True)
+    assert state == 2 and status == M.MCLBM_EUNSTABLE and ran < 1000 and ran % 16 == 0
+    s = M.sim_from_workload(w, precision="f64")
+    s.init()
+    s.step(ran - 16)
+    assert s.diag()["max_u"] <= 0.5
+    s.step(16)
+    assert s.diag()["max_u"] > 0.5
+    for r, rid in zip(good, gids):
+        assert sv.result(rid)[:2] == (2, 0) and sv.steps(rid) == r["nsteps"]
 
 
 def test_unstable_request_is_flagged(M):
