@@ -9,16 +9,16 @@
 // each of four streams a graph of the group's K launches of the batched step
 // kernel, captured once: the kernel reads its table from device memory and
 // runs on a fixed grid, so one graph serves every batch.  A step of a group
-// lasts about as long as one work item (a 64-row march), whatever its size;
-// the groups' steps are independent and run side by side on the hardware
-// queues, so that one group's tail overlaps another's work.  Between rounds the host collects the simulations that
-// have finished (their displacement is copied to the caller's buffer) and
+// lasts about as long as one work item (a march over a chunk of at most 34
+// rows), whatever its size; the groups' steps are independent and run side by
+// side on the hardware queues, so that one group's tail overlaps another's
+// work.  Between rounds the host collects the simulations that have finished (their displacement is copied to the caller's buffer) and
 // admits waiting requests in arrival order while a slot is free and their
 // arena fits in the caller's device pool (first fit).  Requests that arrive
 // while others are on the GPU join at the next round and share its launches.
 // After each round a scan of every active simulation's displacement flags the
-// ones that hold values that are not finite; they end at the next turn as
-// unstable instead of running out their steps.
+// ones that hold values that are not finite or have passed their growth limit;
+// they end at the next turn as unstable instead of running out their steps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
