@@ -276,7 +276,7 @@ const char* mclbm_last_error(void);
  * events, and no device memory.  Single-threaded use. */
 
 typedef struct {
-    int32_t precision;       /* MCLBM_F32 or MCLBM_F64; every request must match  */
+    int32_t precision;       /* enum mclbm_precision; every request must match    */
     int32_t steps_per_round; /* 1..1024                                           */
     int32_t max_active;      /* simulations in flight, 1..1024                    */
 } mclbm_server_config;

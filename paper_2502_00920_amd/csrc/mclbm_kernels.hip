@@ -1125,10 +1125,18 @@ hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipS
         const dim3 grid(batch_blocks<PREC_F64>());
         if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         else hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_NH, 6, 2>), grid, block, 0, st, step);
-    } else {
+    } else if (prec == PREC_F32) {
         const dim3 grid(batch_blocks<PREC_F32>());
         if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         else hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_NH, 6, 2>), grid, block, 0, st, step);
+    } else if (prec == PREC_F16) {
+        const dim3 grid(batch_blocks<PREC_F16>());
+        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F16, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        else hipLaunchKernelGGL((march_batch_kernel<PREC_F16, MAT_NH, 6, 2>), grid, block, 0, st, step);
+    } else {
+        const dim3 grid(batch_blocks<PREC_BF16>());
+        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_BF16, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        else hipLaunchKernelGGL((march_batch_kernel<PREC_BF16, MAT_NH, 6, 2>), grid, block, 0, st, step);
     }
     return hipGetLastError();
 }

@@ -127,8 +127,9 @@ namespace {
 
 int check_config(const mclbm_server_config* c) {
     if (!c) return set_error(MCLBM_EINVAL, "config is NULL");
-    if (c->precision != MCLBM_F64 && c->precision != MCLBM_F32)
-        return set_error(MCLBM_EINVAL, "the server runs FP64 or FP32 storage");
+    if (c->precision != MCLBM_F64 && c->precision != MCLBM_F32 && c->precision != MCLBM_F16 &&
+        c->precision != MCLBM_BF16)
+        return set_error(MCLBM_EINVAL, "unknown storage precision");
     if (c->steps_per_round < 1 || c->steps_per_round > 1024)
         return set_error(MCLBM_EINVAL, "steps_per_round must be in 1..1024");
     if (c->max_active < 1 || c->max_active > 1024) return set_error(MCLBM_EINVAL, "max_active must be in 1..1024");
@@ -220,7 +221,10 @@ MCLBM_EXPORT int mclbm_server_create(const mclbm_server_config* cfg, void* pool,
     mclbm_server* sv = new (std::nothrow) mclbm_server;
     if (!sv) return set_error(MCLBM_EINVAL, "out of host memory");
     sv->cfg = *cfg;
-    sv->prec = cfg->precision == MCLBM_F64 ? PREC_F64 : PREC_F32;
+    sv->prec = cfg->precision == MCLBM_F64   ? PREC_F64
+               : cfg->precision == MCLBM_F32 ? PREC_F32
+               : cfg->precision == MCLBM_F16 ? PREC_F16
+                                             : PREC_BF16;
     sv->pool = static_cast<char*>(pool);
     sv->pool_bytes = pool_bytes;
     sv->stream = static_cast<hipStream_t>(stream);

@@ -146,24 +146,33 @@ def serving_report(n=1000, seed=0, steps=(1000, 20000), load=0.8, baseline=40, *
     cap, cap_s, res = run_closed(reqs, **server_kw)
     # Poisson arrivals at `load` times the closed loop's request rate
     opn = run_open(reqs, rate=load * len(reqs) / cap_s, **server_kw)
+    # the same stream with 16-bit population storage
+    cap16, cap16_s, res16 = run_closed(reqs, precision="f16", **server_kw)
     sub = reqs[:baseline]
     seq, seq_s, useq = run_sequential(sub, "f64")
-    # accuracy of the batched FP32 results against the one-at-a-time FP64 ones
-    errs = []
-    for r in sub:
-        st, status, u = res[r["id"]]
-        ref = useq[r["id"]]
-        if status == 0 and np.all(np.isfinite(ref)) and np.linalg.norm(ref) > 0:
-            errs.append(float(np.linalg.norm(u - ref) / np.linalg.norm(ref)))
+
+    def max_err(batched):
+        # accuracy of batched results against the one-at-a-time FP64 ones
+        errs = []
+        for r in sub:
+            st, status, u = batched[r["id"]]
+            ref = useq[r["id"]]
+            if status == 0 and np.all(np.isfinite(ref)) and np.linalg.norm(ref) > 0:
+                errs.append(float(np.linalg.norm(u - ref) / np.linalg.norm(ref)))
+        return max(errs) if errs else None
+
     return {"workload": f"{n} requests, sides 64..1024, SVK/NH, nu 0..0.45, tension/shear/cantilever, "
                         f"{steps[0]}..{steps[1]} steps, seed {seed}",
             "batched_f32": {"capacity_lups_per_s": cap, "closed_loop_seconds": cap_s,
                             "requests_per_s": len(reqs) / cap_s,
                             "unstable": int(sum(1 for v in res.values() if v[1] != 0))},
             "open_loop_f32": opn,
+            "batched_f16": {"capacity_lups_per_s": cap16, "closed_loop_seconds": cap16_s,
+                            "unstable": int(sum(1 for v in res16.values() if v[1] != 0))},
             "sequential_f64": {"lups_per_s": seq, "requests": len(sub), "seconds": seq_s},
             "speedup_vs_sequential_f64": cap / seq,
-            "batched_f32_vs_sequential_f64_rel_l2_u_max": max(errs) if errs else None}
+            "batched_f32_vs_sequential_f64_rel_l2_u_max": max_err(res),
+            "batched_f16_vs_sequential_f64_rel_l2_u_max": max_err(res16)}
 
 
 def main():

@@ -158,9 +158,9 @@ def test_copy_argument_errors_without_gpu(M):
 
 def test_server_config_validation(M):
     """The server's configuration is checked on the host."""
-    ok = M.mclbm_server_config(M.PRECISION["f32"], 32, 64)
-    assert M.mclbm_server_plan(ok) > 0
-    for bad in [(M.PRECISION["f16"], 32, 64), (M.PRECISION["f32"], 0, 64), (M.PRECISION["f32"], 32, 0),
+    for prec in ("f64", "f32", "f16", "bf16"):
+        assert M.mclbm_server_plan(M.mclbm_server_config(M.PRECISION[prec], 32, 64)) > 0
+    for bad in [(7, 32, 64), (-1, 32, 64), (M.PRECISION["f32"], 0, 64), (M.PRECISION["f32"], 32, 0),
                 (M.PRECISION["f32"], 2000, 64)]:
         with pytest.raises(M.MclbmError) as e:
             M.mclbm_server_plan(M.mclbm_server_config(*bad))

@@ -24,6 +24,9 @@ pytestmark = pytest.mark.gpu
 
 THREADS = min(8, os.cpu_count() or 1)
 TOL = {"f64": 1e-12, "f32": 1e-5}
+# 16-bit storage: no accuracy bound is claimed; regression bounds on the relative
+# L2 distance to the FP64 result (as for the single-lattice path)
+HALF_U = {"f16": 1.5e-3, "bf16": 3e-2}
 
 
 def close(u, ref, precision):
@@ -60,7 +63,7 @@ def alone_via_sim(M, r, precision):
     return s.read("u")
 
 
-@pytest.mark.parametrize("precision", ["f32", "f64"])
+@pytest.mark.parametrize("precision", ["f32", "f64", "f16", "bf16"])
 def test_isolation_bitwise(M, precision):
     print(f"\n[case] server isolation {precision}", flush=True)
     reqs = small_requests(12, seed=3)
@@ -79,9 +82,12 @@ def test_isolation_bitwise(M, precision):
         sid = S._submit(solo, r)
         solo.drain()
         u_alone = solo.result(sid)[2]
-        u_sim = alone_via_sim(M, r, precision)
         assert np.array_equal(u_mix, u_alone), r
-        assert close(u_mix, u_sim, precision), r
+        if precision in TOL:
+            assert close(u_mix, alone_via_sim(M, r, precision), precision), r
+        else:  # against FP64, within the 16-bit storage bound
+            ref = alone_via_sim(M, r, "f64")
+            assert np.linalg.norm(u_mix - ref) <= HALF_U[precision] * np.linalg.norm(ref), r
         del solo
 
 
