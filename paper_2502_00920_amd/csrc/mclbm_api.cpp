@@ -381,7 +381,9 @@ MCLBM_EXPORT int mclbm_step_checked(mclbm_sim* s, int64_t nsteps, int64_t every,
                                s->stream));
         HIP_TRY(hipStreamSynchronize(s->stream));
         if (steps_run) *steps_run = done;
-        if (flag) return fail(MCLBM_EUNSTABLE, "displacement not finite by step %lld", (long long)s->n);
+        if (flag)
+            return fail(MCLBM_EUNSTABLE, "displacement not finite%s by step %lld",
+                        s->p.growth_limit > 0.0 ? " or above the growth limit" : "", (long long)s->n);
     }
     return MCLBM_OK;
 }
