@@ -254,6 +254,43 @@ def test_plane_wave_speeds(nu, kind):
     assert w / (c * k) == pytest.approx(1.0, abs=3e-3)
 
 
+def wave_error(kind, nu, nx, mu=0.05, periods=4.5):
+    """Relative error of a standing plane wave's frequency against c k, from a
+    periodic nx x 3 box (linear law)."""
+    o = make(nx, 3, {s: "periodic" for s in W.SIDES}, mu=mu, nu=nu, material="linear")
+    X, _ = nodes(nx, 3)
+    k = 2 * math.pi / nx
+    comp = 0 if kind == "longitudinal" else 1
+    u0 = np.zeros((2, 3, nx))
+    u0[comp] = 1e-4 * np.sin(k * X)
+    o.init(u0)
+    lam = oracle.plane_strain_lambda(mu, nu)
+    c = math.sqrt((lam + 2 * mu) if kind == "longitudinal" else mu)
+    series = []
+    for _ in range(int(periods * 2 * math.pi / (c * k) / o.dt)):
+        o.step(1)
+        series.append(o.read("u")[comp, 1, 3])
+    return wave_frequency(series, o.dt) / (c * k) - 1
+
+
+@pytest.mark.parametrize("kind,nu", [("longitudinal", 0.0), ("longitudinal", 0.4), ("shear", 0.2)])
+def test_plane_wave_dispersion_is_second_order(kind, nu):
+    """The frequency error of a resolved plane wave falls as (k dX)^2: halving
+    k dX divides it by 4 (a first-order slip in the source or the update would
+    show as a ratio near 2)."""
+    e32, e64 = wave_error(kind, nu, 32), wave_error(kind, nu, 64)
+    print(kind, nu, e32, e64, e32 / e64)
+    assert abs(e32) > 1e-5 and 3.7 < e32 / e64 < 4.4
+
+
+def test_wave_at_the_lattice_speed_is_exact():
+    """At nu = 1/4 the dilatational speed equals the lattice speed (c_d = sqrt(3) c_s
+    = c, Sect. 3.2), the source vanishes for the linear law, and an axis-aligned
+    longitudinal wave moves exactly one node per step: no dispersion at all, even
+    on a coarse lattice."""
+    assert abs(wave_error("longitudinal", 0.25, 16)) < 1e-12
+
+
 # ---- finite differences and load programs ---------------------------------------------
 
 def test_finite_difference_rules():
