@@ -71,6 +71,84 @@ def test_rigid_translation(material):
     np.testing.assert_allclose(o.read("j"), j0, atol=1e-15)
 
 
+def test_rigid_translation_between_moving_dirichlet_walls():
+    """All four walls Dirichlet with j* = rho0 v0 (the body's own momentum): the
+    modified bounce-back of Eq. bbcon reflects each equilibrium population into
+    its opposite exactly, so the uniform motion is again a discrete steady state
+    and u moves by dt v0 per step."""
+    nx, ny = 9, 7
+    v0 = np.array([0.0025, -0.00125])
+    rho0 = 1.0
+    o = make(nx, ny, {s: ("dirichlet", "const", tuple(rho0 * v0)) for s in W.SIDES})
+    j0 = np.zeros((2, ny, nx))
+    j0[0], j0[1] = rho0 * v0[0], rho0 * v0[1]
+    o.init(j0=j0)
+    f0 = o.read_f()
+    n = 30
+    o.step(n)
+    u = o.read("u")
+    expect = np.zeros_like(u)
+    expect[0], expect[1] = n * o.dt * v0[0], n * o.dt * v0[1]
+    assert relerr(u, expect) < 1e-13
+    np.testing.assert_allclose(o.read_f(), f0, atol=1e-15)
+
+
+def test_body_force_momentum_balance():
+    """Periodic box with a body force b: the divergence of T sums to zero over a
+    periodic lattice, so the total momentum sum_X sum_q c_q f_q grows by exactly
+    dt N rho0 b per step (the source of Eq. source enters the collision and the
+    moment so that each node gains dt S), whatever the state."""
+    nx, ny, rho0 = 12, 10, 1.0
+    b = np.array([2e-4, -1.5e-4])
+    o = make(nx, ny, {s: "periodic" for s in W.SIDES}, body=tuple(b))
+    o.init(W.smooth_field(nx, ny, 0.02, 3) + W.random_field(nx, ny, 1e-4, 4), W.random_field(nx, ny, 1e-3, 5))
+    m = [o.momentum()]
+    for _ in range(6):
+        o.step(1)
+        m.append(o.momentum())
+    gain = np.diff(np.array(m), axis=0)
+    expect = o.dt * nx * ny * rho0 * b
+    np.testing.assert_allclose(gain, np.broadcast_to(expect, gain.shape), rtol=1e-11, atol=0)
+
+
+def test_diagonal_mirror_symmetry():
+    """A square lattice with four traction-free walls is symmetric under the
+    reflection across its diagonal (x <-> y, u_x <-> u_y), as is the D2Q9 velocity
+    set and an isotropic material: a start with that symmetry keeps it.  This
+    pins the corner rule's treatment of the two walls as equals (the shear entry
+    of the corner's Pi_bd is their mean), which a mirror across a lattice axis
+    does not see."""
+    n = 14
+    o = make(n, n, {s: "neumann" for s in W.SIDES}, nu=0.2)
+    a = W.smooth_field(n, n, 0.01, 6)[0] + W.random_field(n, n, 1e-4, 7)[0]
+    u0 = np.stack([a, a.T])
+    o.init(u0)
+    o.step(80)
+    u = o.read("u")
+    scale = np.abs(u).max()
+    assert scale > 1e-3
+    np.testing.assert_allclose(u[0], u[1].T, atol=1e-12 * scale)
+
+
+def test_zeroth_moment_tracks_the_divergence_of_u():
+    """r obeys d_t r + Div j = 0 (Sect. 3.1) and j = rho0 du/dt, so the dynamics
+    keep r = -rho0 Div u once the start has it (Algorithm 1's initial state): on a
+    smooth periodic field the relation holds after many steps to the
+    finite-difference error, far below the field itself."""
+    nx, ny = 48, 40
+    X, Y = nodes(nx, ny)
+    kx, ky = 2 * math.pi / nx, 2 * math.pi / ny
+    u0 = np.stack([1e-3 * np.sin(kx * X) * np.cos(ky * Y), 7e-4 * np.cos(kx * X) * np.sin(2 * ky * Y)])
+    o = make(nx, ny, {s: "periodic" for s in W.SIDES}, nu=0.2, material="linear")
+    o.init(u0)
+    o.step(60)
+    H = o.read("h")
+    div = -(H[0] + H[3])  # rho0 = 1
+    r = o.read("r")[0]
+    assert np.abs(o.read("u") - u0).max() > 0.2 * np.abs(u0).max()  # the field has moved on
+    assert relerr(r, div) < 0.02
+
+
 # ---- homogeneous steady states ---------------------------------------------------
 
 @pytest.mark.parametrize("material", ["svk", "neohooke"])
