@@ -385,6 +385,30 @@ def test_rigid_translation_at_size(M):
     assert np.abs(u[1] - 30 * s.dt * v0[1]).max() < 1e-14
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_rigid_translation_between_moving_walls_at_size(M, precision):
+    """All four walls Dirichlet with j* = rho0 v0 on the benchmark's lattice size
+    and launch shape: the bounce-back reflects the uniform equilibrium exactly, so
+    every node moves by dt v0 per step (the oracle's pin of the same state, here
+    at a size the oracle does not reach in a test)."""
+    print_case(f"rigid translation between moving walls 8192x8192 {precision}")
+    n = 8192
+    v0 = (0.0025, -0.00125)
+    s = M.Sim(n, n, mu=0.05, nu=0.3, tau=0.55, material="svk", precision=precision)
+    for side in W.SIDES:
+        s.set_side(side, "dirichlet", "const", v0)
+    j0 = np.empty((2, n, n))
+    j0[0], j0[1] = v0
+    s.init(None, j0)
+    del j0
+    s.step(5)
+    u = s.read("u")
+    tol = 1e-14 if precision == "f64" else 1e-7
+    assert np.abs(u[0] - 5 * s.dt * v0[0]).max() <= tol * 5 * s.dt * abs(v0[0])
+    assert np.abs(u[1] - 5 * s.dt * v0[1]).max() <= tol * 5 * s.dt * abs(v0[1])
+    del s
+
+
 # ---- determinism, checkpoints, diagnostics ------------------------------------------------------
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
