@@ -201,11 +201,11 @@ def serving(n: int = 200, steps=(1000, 4000), baseline: int = 20) -> dict:
     return serve.serving_report(n=n, steps=steps, baseline=baseline)
 
 
-def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
+def ingest_counters(fetch_dir: str, write_dir: str, n: int, out_path: str = TRAFFIC_FILE) -> dict:
     """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE;
     counter values in KiB per dispatch) into HBM bytes per launch of
     march_kernel, each counter scaled by what it reads for the library's copy
-    kernel moving COPY_BYTES; writes TRAFFIC_FILE."""
+    kernel moving COPY_BYTES; writes out_path (the traffic file by default)."""
     import csv
     import glob
 
@@ -239,7 +239,7 @@ def ingest_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
             out[m] = {"nodes": n * n, "fetch_size_bytes": fetch[m], "write_size_bytes": write[m],
                       "read_bytes": rd, "written_bytes": wr, "bytes_per_launch": rd + wr,
                       "algorithmic_bytes": alg, "ratio": (rd + wr) / alg}
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     return out
@@ -343,7 +343,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the time step of one "
-              "lattice runs on a single MI355X; see DESIGN.md for how it would shard)", file=sys.stderr)
+              "lattice runs on a single MI355X; across GPUs the lattice would split into slabs along y "
+              "with one halo exchange per step)", file=sys.stderr)
         sys.exit(2)
 
     import torch
