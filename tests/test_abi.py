@@ -65,6 +65,16 @@ def test_plan_validation(M):
         assert e.value.code == M.MCLBM_EINVAL
     M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, tau_plus=0.8))  # the option is accepted
     M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, growth_limit=2.5))
+    # the largest lattices: each 32-bit buffer range of planes must stay below 4 GiB
+    for n, prec, ok in ((16320, "f32", True), (16384, "f32", False), (16320, "bf16", True),
+                        (13376, "f64", True), (13440, "f64", False)):
+        p = M.make_params(n, n, mu=0.05, nu=0.3, tau=0.55, precision=prec)
+        if ok:
+            assert M.mclbm_plan(p)[0] > 0
+        else:
+            with pytest.raises(M.MclbmError) as e:
+                M.mclbm_plan(p)
+            assert e.value.code == M.MCLBM_EINVAL
     p = M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0)
     p.material = 7
     with pytest.raises(M.MclbmError):
