@@ -409,6 +409,34 @@ def test_rigid_translation_between_moving_walls_at_size(M, precision):
     del s
 
 
+@pytest.mark.parametrize("n,precision", [(16320, "f32"), (13376, "f64")])
+def test_largest_lattice(M, n, precision):
+    """The largest square lattice the plan admits for the storage format, where
+    the 32-bit buffer offsets of the kernels come within a few percent of 4 GiB:
+    the homogeneous uniaxial tension state (u linear in X, so a node that read
+    another node's values would show) stays put and carries the closed-form
+    stress, at every node."""
+    print_case(f"largest lattice {n}x{n} {precision}")
+    mu, nu, l1 = 0.05, 0.2, 1.0625
+    l2 = math.sqrt((1 - nu * l1 ** 2) / (1 - nu))
+    P11 = mu * l1 * (l1 ** 2 - 1) / (1 - nu)
+    x = np.arange(n) + 0.5
+    u0 = np.empty((2, n, n))
+    u0[0] = (l1 - 1) * x[None, :]
+    u0[1] = (l2 - 1) * x[:, None]
+    s = M.Sim(n, n, mu=mu, nu=nu, tau=0.55, material="svk", precision=precision)
+    s.set_side("left", "neumann", "const", (-P11, 0.0))
+    s.set_side("right", "neumann", "const", (P11, 0.0))
+    s.init(u0)
+    s.step(3)
+    tol = 1e-12 if precision == "f64" else 1e-6
+    assert rel(s.read("u"), u0) < tol
+    del u0
+    P = s.read("p")
+    assert np.abs(P[0] / P11 - 1).max() < (1e-9 if precision == "f64" else 1e-3)
+    del P, s
+
+
 # ---- determinism, checkpoints, diagnostics ------------------------------------------------------
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
