@@ -252,6 +252,29 @@ def test_tension8192_full_size(M, precision):
 
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_neohooke_full_size(M, precision):
+    """The benchmark's lattice and walls with the neo-Hooke law (its stress pass
+    has a division and a different operation count): every node against the
+    oracle after 2 steps."""
+    print_case(f"neo-Hooke 8192x8192 {precision}")
+    w = W.tension_large(8192, 1000)
+    n = w.nx
+    u0 = W.smooth_field(n, n, 0.02, seed=31) + W.random_field(n, n, 1e-4, seed=32)
+    j0 = W.random_field(n, n, 1e-3, seed=33)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    o, s = pair(M, n, n, {k: (v.bc, v.kind, v.amp, v.t0, v.t1, v.width) for k, v in w.sides.items()},
+                material="neohooke", mu=w.mu, nu=w.nu, tau=w.tau, precision=precision, u0=u0, j0=j0,
+                threads=max(1, min(16, cores)))
+    del u0, j0
+    o.step(2)
+    s.step(2)
+    e = compare(o, s, ("u", "p"))
+    print({f: f"{v:.2e}" for f, v in e.items()}, flush=True)
+    assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], e
+    del o, s
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_ragged_large_lattice(M, precision):
     """8190 x 8191: the long chunks of the benchmark's launch shape (64 rows in
     FP32, 34 in FP64) with a ragged last strip (62 of 64 columns) and a short last
