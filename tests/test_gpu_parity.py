@@ -567,6 +567,21 @@ def test_step_checked(M):
     assert not ok and ran < 3000 and ran % 100 == 0 and s.diag()["nonfinite"]
 
 
+def test_injected_nan_is_caught(M):
+    """A NaN placed in u0 at one node (independent of any physics): checked steps
+    stop at their first check and the diagnostics flag it."""
+    print_case("injected NaN")
+    nx, ny = 70, 45
+    u0 = W.smooth_field(nx, ny, 0.01, 8)
+    u0[1, 20, 33] = np.nan
+    for precision in ("f64", "f32"):
+        s = M.Sim(nx, ny, mu=0.05, nu=0.2, tau=0.55, material="svk", precision=precision)
+        s.init(u0)
+        ok, ran = s.step_checked(100, every=10)
+        assert not ok and ran == 10, (precision, ran)
+        assert s.diag()["nonfinite"]
+
+
 def test_growth_limit(M):
     """A growth limit on |u|: checked steps stop at the first check whose
     maximum displacement (as the diagnostics report it on an unlimited twin run)

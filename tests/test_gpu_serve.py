@@ -184,6 +184,20 @@ def test_growth_limit_stops_a_request(M):
         assert sv.result(rid)[:2] == (2, 0) and sv.steps(rid) == r["nsteps"]
 
 
+def test_injected_nan_request_stops_at_the_first_round(M):
+    print("\n[case] server stops a request whose u0 holds a NaN", flush=True)
+    good = small_requests(2, seed=11)
+    sv = M.Server(precision="f32", steps_per_round=16, max_active=4, pool_bytes=64 << 20)
+    u0 = np.zeros((2, 40, 50))
+    u0[0, 10, 10] = np.nan
+    bid = sv.submit(50, 40, mu=0.05, nu=0.2, tau=0.55, material="svk", sides={}, nsteps=500, u0=u0)
+    gids = [S._submit(sv, r) for r in good]
+    sv.drain()
+    assert sv.result(bid)[:2] == (2, M.MCLBM_EUNSTABLE) and sv.steps(bid) == 16
+    for r, rid in zip(good, gids):
+        assert sv.result(rid)[:2] == (2, 0) and sv.steps(rid) == r["nsteps"]
+
+
 def test_unstable_request_is_flagged(M):
     print("\n[case] server flags a diverging request", flush=True)
     rng = np.random.default_rng(1)
