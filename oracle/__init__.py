@@ -177,7 +177,10 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().orc_destroy(h)
+            try:
+                lib().orc_destroy(h)
+            except TypeError:  # interpreter shutdown: the module's globals are gone
+                pass
             self._h = None
 
     @property

@@ -191,15 +191,25 @@ def test_tension32(M, precision):
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_shear128(M, precision):
     print_case(f"shear128 nu=0.25 {precision}")
-    for n, e, umax in run_workload(M, W.shear128(0.25), precision, [200, 1000]):
+    for n, e, umax in run_workload(M, W.shear128(0.25), precision, [200, 1000, 2000]):
         assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_beam2048(M, precision):
+    """The cantilever pulse (Gaussian traction, 2048 x 128) through its pulse and
+    well into the free vibration that follows: 3000 of its 50000 steps (it loses
+    stability near step 21000).  The rounding differences between two FP64
+    implementations (different operation order, contraction to fused
+    multiply-adds in the kernel) accumulate over the free vibration: P differs
+    by 2.7e-13 at step 1000, 1.75e-12 at 2000, 3.6e-12 at 3000 and 5.7e-12 at
+    4000 (u by 30 times less).  The FP64 bar of 1e-12 is asserted to step 1000;
+    at step 3000 a long-horizon bound of 1e-11 is.  FP32 stays below 2e-6 and
+    keeps its bar of 1e-5 throughout."""
     print_case(f"beam2048x128 {precision}")
-    for n, e, umax in run_workload(M, W.beam2048(), precision, [50, 150]):
-        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+    for n, e, umax in run_workload(M, W.beam2048(), precision, [50, 150, 1000, 3000]):
+        tol = 1e-11 if precision == "f64" and n > 1000 else TOL[precision]
+        assert e["u"] <= tol and e["p"] <= tol, (n, e)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
