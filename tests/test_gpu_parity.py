@@ -196,6 +196,19 @@ def test_shear128(M, precision):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("nu,checkpoints", [(0.0, [200, 1000]), (0.45, [5, 10]), (0.49, [3, 6])])
+def test_shear128_poisson_sweep(M, nu, checkpoints, precision):
+    """The other Poisson ratios of the 128 x 128 neo-Hooke shear workload, inside
+    the range where the run is still finite: nu = 0 diverges after about 2750
+    steps; 0.45 and 0.49, beyond the CFL bounds of Sect. 3.2, within tens of steps,
+    and the growing modes amplify rounding differences from the start."""
+    print_case(f"shear128 nu={nu} {precision}")
+    for n, e, umax in run_workload(M, W.shear128(nu), precision, checkpoints):
+        assert np.isfinite(umax)
+        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_beam2048(M, precision):
     """The cantilever pulse (Gaussian traction, 2048 x 128) through its pulse and
     well into the free vibration that follows: 3000 of its 50000 steps (it loses
