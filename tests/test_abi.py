@@ -175,3 +175,37 @@ def test_server_config_validation(M):
         with pytest.raises(M.MclbmError) as e:
             M.mclbm_server_plan(M.mclbm_server_config(*bad))
         assert e.value.code == M.MCLBM_EINVAL
+
+
+def test_product_never_reaches_the_oracle():
+    """The oracle is test infrastructure: no module of the package names it, and
+    importing every module of the package (the HIP binding included) leaves it
+    unloaded."""
+    pkg = os.path.join(ROOT, "paper_2502_00920_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            if name.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, name), errors="replace").read()
+                assert "import oracle" not in text and "from oracle" not in text, name
+                assert "liboracle" not in text and "mclbm_oracle" not in text, name
+    code = ("import sys; import paper_2502_00920_amd.mclbm, paper_2502_00920_amd.serve, "
+            "paper_2502_00920_amd.paper_cases, paper_2502_00920_amd.workloads, paper_2502_00920_amd.build; "
+            "assert 'oracle' not in sys.modules, 'oracle loaded'; print('clean')")
+    p = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0 and "clean" in p.stdout, p.stderr[-2000:]
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without libmclbm.so: importing the binding raises
+    (there is no CPU fallback to route to)."""
+    import shutil
+    dst = tmp_path / "paper_2502_00920_amd"
+    dst.mkdir()
+    for name in os.listdir(os.path.join(ROOT, "paper_2502_00920_amd")):
+        if name.endswith(".py"):
+            shutil.copy(os.path.join(ROOT, "paper_2502_00920_amd", name), dst / name)
+    code = ("import sys; sys.path.insert(0, sys.argv[1])\n"
+            "try:\n    import paper_2502_00920_amd.mclbm\nexcept ImportError as e:\n"
+            "    print('raised:', e); sys.exit(0)\nsys.exit(1)")
+    p = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True, timeout=300)
+    assert p.returncode == 0 and "no fallback" in p.stdout, (p.stdout, p.stderr[-1000:])
