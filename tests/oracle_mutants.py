@@ -63,6 +63,26 @@ MUT = [
  ("linear extrapolation sign", "0.5 * (3.0 * (arr)[i] - (arr)[ii])", "0.5 * (3.0 * (arr)[i] + (arr)[ii])"),
  ("second-order one-sided coefficient", "s * (-3.0 * AT(0) + 4.0 * AT(1) - AT(2))", "s * (-3.0 * AT(0) + 4.0 * AT(1) + AT(2))"),
  ("cq y from EX", "h->cq[q][1] = h->c * EY[q];", "h->cq[q][1] = h->c * EX[q];"),
+ ("one diagonal weight", "1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0}", "1.0 / 36.0, 1.0 / 32.0, 1.0 / 36.0, 1.0 / 36.0}"),
+ ("one velocity sign", "static const int EY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};", "static const int EY[9] = {0, 0, 1, 0, -1, 1, -1, -1, -1};"),
+ ("feq r term sign", "double Axx = Pi[0] - r * cs2, Axy = Pi[1], Ayy = Pi[2] - r * cs2;", "double Axx = Pi[0] + r * cs2, Axy = Pi[1], Ayy = Pi[2] + r * cs2;"),
+ ("psi transposed", "out[q] = W[q] * (cq[q][0] * S[0] + cq[q][1] * S[1]) / cs2;", "out[q] = W[q] * (cq[q][1] * S[0] + cq[q][0] * S[1]) / cs2;"),
+ ("collision Pi_xy moment", "        pxy += cq[q][0] * cq[q][1] * f[q];\n        pyy += cq[q][1] * cq[q][1] * f[q];\n    }\n    double jj[2] = {mx + 0.5 * dt * S[0], my + 0.5 * dt * S[1]};\n    double Pi3[3] = {pxx, pxy, pyy};\n    double feq[9], psi[9];\n    orc_feq(cs2, cq, r, jj, Pi3, feq);\n    orc_psi(cs2, cq, S, psi);\n    for (int q = 0; q < 9; q++)\n        out[q] = f[q] - omega", "        pxy += cq[q][0] * cq[q][0] * f[q];\n        pyy += cq[q][1] * cq[q][1] * f[q];\n    }\n    double jj[2] = {mx + 0.5 * dt * S[0], my + 0.5 * dt * S[1]};\n    double Pi3[3] = {pxx, pxy, pyy};\n    double feq[9], psi[9];\n    orc_feq(cs2, cq, r, jj, Pi3, feq);\n    orc_psi(cs2, cq, S, psi);\n    for (int q = 0; q < 9; q++)\n        out[q] = f[q] - omega"),
+ ("TRT forcing at the even rate", "out[q] = f[q] - omega_plus * even - omega * odd + (1.0 - 0.5 * omega) * psi[q] * dt;", "out[q] = f[q] - omega_plus * even - omega * odd + (1.0 - 0.5 * omega_plus) * psi[q] * dt;"),
+ ("Pi(H) yy from H_xx", "Pi[3] = -(mu * (H[3] + H[3]) + mu * tr);", "Pi[3] = -(mu * (H[0] + H[0]) + mu * tr);"),
+ ("NH det C sign", "double detC = C[0][0] * C[1][1] - C[0][1] * C[1][0];", "double detC = C[0][0] * C[1][1] + C[0][1] * C[1][0];"),
+ ("source y axes swapped", "(fd(h, T + 2 * N, x, y, 0) + fd(h, T + 3 * N, x, y, 1));", "(fd(h, T + 2 * N, x, y, 1) + fd(h, T + 3 * N, x, y, 0));"),
+ ("inward neighbour outward", "int xi = x - (a == 0 ? (int)s : 0), yi = y - (a == 1 ? (int)s : 0);", "int xi = x + (a == 0 ? (int)s : 0), yi = y + (a == 1 ? (int)s : 0);"),
+ ("traction at the next step", "    side_value(h, side, n, Ts);", "    side_value(h, side, n + 1, Ts);"),
+ ("wall momentum at the next step", "double v[2]; side_value(h, wx, n, v);", "double v[2]; side_value(h, wx, n + 1, v);"),
+ ("corner j* not averaged", "js[0] /= nd; js[1] /= nd;", "js[0] /= 1; js[1] /= 1;"),
+ ("initial j_y from j_x", "double jj[2] = {j0 ? j0[i] : 0.0, j0 ? j0[N + i] : 0.0};", "double jj[2] = {j0 ? j0[i] : 0.0, j0 ? j0[i] : 0.0};"),
+ ("periodic x wrap shifted", "if (px) xt = (xt + nx) % nx;", "if (px) xt = (xt + nx + 1) % nx;"),
+ ("linear ramp one step late", "case LOAD_LINEAR_RAMP: return n < s->t1 ? n / s->t1 : 1.0;", "case LOAD_LINEAR_RAMP: return n < s->t1 ? (n + 1) / s->t1 : 1.0;"),
+ ("sin pulse period", "case LOAD_SIN_PULSE: return n < s->t1 ? sin(M_PI * n / s->t1) : 0.0;", "case LOAD_SIN_PULSE: return n < s->t1 ? sin(2.0 * M_PI * n / s->t1) : 0.0;"),
+ ("Ricker amplitude", "double a = 2.0 / sqrt(3.0 * s->width * sqrt(M_PI));", "double a = 1.0 / sqrt(3.0 * s->width * sqrt(M_PI));"),
+ ("update without rho0", "h->un[i] = h->u[i] + dt / (2.0 * h->rho0) * (jx + h->jA[i]);", "h->un[i] = h->u[i] + dt / 2.0 * (jx + h->jA[i]);"),
+ ("trapezoid uses new j twice", "h->un[N + i] = h->u[N + i] + dt / (2.0 * h->rho0) * (jy + h->jA[N + i]);", "h->un[N + i] = h->u[N + i] + dt / (2.0 * h->rho0) * (jy + jy);"),
 ]
 TESTS = ["tests/test_oracle_blocks.py", "tests/test_oracle_invariants.py", "tests/test_paper_cases.py"]
 

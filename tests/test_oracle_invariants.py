@@ -3,11 +3,15 @@
 Properties the time step of Algorithm 1 must have for any correct
 implementation, each chosen so that a plausible slip (a dropped term, a wrong
 sign or index, a wrong time level) breaks one of them:
-  rest state, rigid translation, homogeneous uniaxial and simple-shear steady
-  states, discrete momentum balance under Neumann walls, mirror symmetry,
-  independence of the shear modulus in lattice units, plane-wave speeds of the
-  source-corrected chain, the finite-difference rules, the boundary load
-  programs and the bulk stability bound the paper states.
+  rest state, rigid translation (between free walls, between moving Dirichlet
+  walls, and carried to the end of a displacement ramp), homogeneous uniaxial
+  and simple-shear steady states, discrete momentum balance under Neumann walls
+  and under a body force, mirror symmetry across a lattice axis and across the
+  diagonal, r following -rho0 Div u, independence of the shear modulus in
+  lattice units, plane-wave speeds of the source-corrected chain with
+  second-order dispersion and none at the lattice speed, the finite-difference
+  rules, the boundary load programs and the bulk stability bound the paper
+  states.
 """
 import math
 
@@ -478,6 +482,34 @@ def test_load_programs():
         g = (2 / math.sqrt(3 * s * math.sqrt(math.pi)) * (1 - (n - t0) ** 2 / s)
              * math.exp(-0.5 * (n - t0) ** 2 / s)) if n < 60 else 0.0
         np.testing.assert_allclose(o.side_value("top", n), [0, 0.15 * g], atol=1e-16, rtol=1e-14)
+
+
+def test_linear_ramp_and_constant_programs():
+    o = make(8, 8, {"left": ("neumann", "linear_ramp", (0.2, -0.1), 0, 40),
+                    "right": ("neumann", "const", (0.3, 0.05))})
+    for n in [0, 1, 20, 39, 40, 41, 100]:
+        g = n / 40 if n < 40 else 1.0
+        np.testing.assert_allclose(o.side_value("left", n), [0.2 * g, -0.1 * g], rtol=1e-15, atol=0)
+        np.testing.assert_allclose(o.side_value("right", n), [0.3, 0.05], rtol=1e-15)
+
+
+def test_walls_on_a_displacement_ramp_carry_the_body_to_its_end():
+    """Four Dirichlet walls on the same displacement ramp (A over t1 steps) and a
+    start at the matching uniform momentum: the body translates rigidly, and
+    after exactly t1 steps every node has moved by A.  This fixes the time level
+    of j* in the bounce-back (step n's value for step n's collision, Sect. 3.3):
+    walls one step ahead would stop a step early."""
+    nx, ny, t1 = 9, 7, 24
+    A = np.array([0.75, -0.375])
+    o = make(nx, ny, {s: ("dirichlet", "disp_ramp", tuple(A), 0, t1) for s in W.SIDES})
+    v0 = A / (t1 * o.dt)
+    j0 = np.zeros((2, ny, nx))
+    j0[0], j0[1] = v0[0], v0[1]
+    o.init(j0=j0)
+    o.step(t1)
+    u = o.read("u")
+    np.testing.assert_allclose(u[0], A[0], rtol=1e-13)
+    np.testing.assert_allclose(u[1], A[1], rtol=1e-13)
 
 
 def test_gauss_pulse_program():
