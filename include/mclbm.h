@@ -56,10 +56,13 @@ enum mclbm_material { MCLBM_SVK = 0, MCLBM_NEOHOOKE = 1, MCLBM_LINEAR = 2 };
  * u is stored and integrated in FP64 in every mode, and its differences (the
  * displacement gradient) are taken in FP64.
  *   F64   populations FP64, arithmetic FP64 (the plain method)
- *   F32   populations stored in FP32; stresses, source, pulls and wall rules in
- *         FP32; the moments, the equilibrium and the BGK relaxation in FP64
- *         (the D2Q9 weights are inexact in FP32, and an FP32 equilibrium
- *         would scale j and Pi by about 1 + 1e-8 in every collision)
+ *   F32   populations stored in FP32; stresses, source and pulls in FP32; the
+ *         moments, the equilibrium and the BGK relaxation in FP64 (the D2Q9
+ *         weights are inexact in FP32, and an FP32 equilibrium would scale j
+ *         and Pi by about 1 + 1e-8 in every collision); at wall nodes the
+ *         stresses and the wall rules, i.e. the boundary-traction balance
+ *         Pi N = -T* + (P + Pi(H)) N of Sect. 3.3 and the bounce-back values,
+ *         in FP64 (T* and P(H) N nearly cancel on a loaded wall)
  *   F16   populations stored as FP16, arithmetic as F32.  The rest state of the
  *         scheme has f = 0, so the stored values are the deviations from that
  *         equilibrium; they are kept times 2^(12 - floor(log2 rho0)), which
@@ -91,12 +94,15 @@ enum mclbm_bc { MCLBM_DIRICHLET = 0, MCLBM_NEUMANN = 1, MCLBM_PERIODIC = 2 };
  *   RICKER      amp * 2/sqrt(3 width sqrt(pi)) (1 - (n-t0)^2/width)
  *               * exp(-(n-t0)^2 / (2 width)) for n < t1, 0 after (Eq. of the
  *               Ricker wavelet in Sect. 4.3, s = width, times in steps)
+ *   TABLE       amp * table[n] for n < table_len, amp * table[table_len - 1]
+ *               after (any load history sampled at the steps; the table is
+ *               copied when the side is set)
  * For a Dirichlet wall the value is j* (momentum density), for a Neumann wall
  * T* (traction, force per reference length). */
 enum mclbm_load_kind {
     MCLBM_LOAD_ZERO = 0, MCLBM_LOAD_CONST = 1, MCLBM_LOAD_DISP_RAMP = 2,
     MCLBM_LOAD_LINEAR_RAMP = 3, MCLBM_LOAD_SIN2_RAMP = 4, MCLBM_LOAD_SIN_PULSE = 5,
-    MCLBM_LOAD_GAUSS = 6, MCLBM_LOAD_RICKER = 7
+    MCLBM_LOAD_GAUSS = 6, MCLBM_LOAD_RICKER = 7, MCLBM_LOAD_TABLE = 8
 };
 
 /* Fields for mclbm_read, at t_n after n steps:
@@ -139,6 +145,41 @@ typedef struct {
                            * mclbm_diag sets growth and returns EUNSTABLE, and
                            * mclbm_step_checked stops, like for a non-finite
                            * value.  In units of length, like dx.               */
+    int32_t extrap;       /* Neumann walls (Sect. 3.3): the stresses in the
+                           * quasi-boundary traction -T* + (P + Pi(H)) N and the
+                           * entry of Pi_bd the traction does not set are carried
+                           * from the wall node X to the half-way wall.
+                           * 0: zeroth order, the node's value (default).
+                           * 1: linear, (3 v(X) - v(X - N dX)) / 2; with the
+                           * one-sided source differences of Sect. 3.2 this
+                           * closes the discrete momentum balance exactly.     */
+    int32_t corner;       /* the shear entry of Pi_bd for a link that crosses
+                           * two Neumann walls (the paper gives no corner rule):
+                           * 0 the mean of the two walls' entries (default),
+                           * 1 the x wall's, 2 the y wall's.                     */
+    int32_t boundary_order; /* one-sided differences (u -> H, T -> S) at the
+                           * outermost nodes: 1 first order, with the inward
+                           * neighbour (Sect. 3.2; default); 2 second order,
+                           * (-3 v0 + 4 v1 - v2) / (2 dX), the stencils for which
+                           * the CFL discussion of Sect. 3.2 admits nu <= 5/11.
+                           * 2 runs the multi-pass step (see time_levels).      */
+    int32_t time_levels;  /* 0: the stresses and the source of step n are taken
+                           * from u_n before the collision, so the collision,
+                           * the moment j(t_{n+1}) and the walls all use level n
+                           * (Sect. 3.1 states S at the current level; default).
+                           * 1: the order printed in Algorithm 1: the collision
+                           * and the walls of step n use S and T of level n - 1
+                           * (from u_{n-1}), j(t_{n+1}) uses S_n.  Options 1 and
+                           * boundary_order 2 run a multi-pass step (stresses,
+                           * source, then the step, three launches, FP64
+                           * arithmetic) with S and T held in the arena; the
+                           * default runs one fused launch.                     */
+    int32_t diag_every;   /* 0: off.  k > 0: mclbm_step runs the diagnostics on
+                           * the device after every step whose count is a
+                           * multiple of k, without synchronising, and records
+                           * the first such step at which u or j was not finite
+                           * (mclbm_diag_out.first_bad_step).                   */
+    int32_t reserved_;    /* must be 0                                          */
 } mclbm_params;
 
 typedef struct {
@@ -146,6 +187,9 @@ typedef struct {
     int32_t kind;         /* enum mclbm_load_kind                               */
     double amp[2];        /* load vector                                        */
     double t0, t1, width; /* time-program parameters, in steps                  */
+    const double* table;  /* TABLE: the scalar program per step (host memory,
+                           * copied by mclbm_set_side / mclbm_server_submit)   */
+    int64_t table_len;    /* TABLE: entries, 1..2^26; other kinds ignore both   */
 } mclbm_side_spec;
 
 typedef struct {
@@ -158,17 +202,23 @@ typedef struct {
     int32_t cfl_excess;   /* 1 when the dilatational wave speed exceeds the
                            * lattice speed, c_d > c, i.e. nu > 1/4: beyond the
                            * CFL bound of first-order boundary stencils
-                           * (Sect. 3.2).  A warning about the parameters, not
-                           * an error: such runs often diverge near walls.     */
+                           * (Sect. 3.2); with boundary_order 2, when nu > 5/11.
+                           * A warning about the parameters, not an error: such
+                           * runs often diverge near walls.                     */
+    int32_t pad_;
+    int64_t first_bad_step; /* diag_every > 0: the first step checked during
+                           * mclbm_step at which u or j was not finite, -1 when
+                           * none (or diag_every = 0)                          */
 } mclbm_diag_out;
 
 typedef struct mclbm_sim mclbm_sim; /* opaque host-side handle */
 
-/* Arena size for these parameters and the derived time step dt (either output
- * pointer may be NULL).  Host only; validates the parameters.  Returns
- * EINVAL for nx or ny < 3, dx, rho0 or mu <= 0, tau <= 0.5, nu outside
- * (-1, 0.5) or unknown enums. */
-int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, double* dt_out);
+/* Arena size for these parameters, the alignment the arena needs (256 bytes)
+ * and the derived time step dt (any output pointer may be NULL).  Host only;
+ * validates the parameters.  Returns EINVAL for nx or ny < 3, dx, rho0 or
+ * mu <= 0, tau <= 0.5, nu outside (-1, 0.5), unknown enums or option values,
+ * or reserved_ != 0. */
+int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, size_t* align, double* dt_out);
 
 /* Create a simulation on the current HIP device inside the caller's arena
  * (device pointer, at least mclbm_plan bytes, 256-byte aligned) and stream
@@ -234,12 +284,17 @@ int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device);
  * max_u exceeds the growth_limit. */
 int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out);
 
-/* Checkpoints: the bytes of the state (populations, displacement, step
- * counter) and copies of it to or from host / device memory.  A simulation
- * loaded from a checkpoint continues bitwise as the one saved. */
+/* Checkpoints: a 64-byte header (magic, format version, nx, ny, storage
+ * precision, material, byte counts, step counter) followed by the state
+ * (populations, displacement, and with time_levels = 1 the source and stresses
+ * of the previous level), copied to or from host (on_device = 0) or device
+ * (on_device = 1) memory of at least mclbm_state_bytes bytes.  A simulation
+ * loaded from a checkpoint continues bitwise as the one saved.  mclbm_load
+ * returns EINVAL, leaving the simulation as it was, when src_bytes is short or
+ * the header does not match this simulation's lattice, storage and options. */
 size_t mclbm_state_bytes(const mclbm_sim* s);
-int mclbm_save(mclbm_sim* s, void* dst, int on_device);
-int mclbm_load(mclbm_sim* s, const void* src, int on_device);
+int mclbm_save(mclbm_sim* s, void* dst, size_t dst_bytes, int on_device);
+int mclbm_load(mclbm_sim* s, const void* src, size_t src_bytes, int on_device);
 
 /* Release the host handle (the arena stays with the caller). */
 int mclbm_destroy(mclbm_sim* s);

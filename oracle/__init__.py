@@ -23,7 +23,7 @@ SIDE = {"left": 0, "right": 1, "bottom": 2, "top": 3}
 BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
 MATERIAL = {"svk": 0, "neohooke": 1, "linear": 2}
 LOAD = {"zero": 0, "const": 1, "disp_ramp": 2, "linear_ramp": 3, "sin2_ramp": 4,
-        "sin_pulse": 5, "gauss": 6, "ricker": 7}
+        "sin_pulse": 5, "gauss": 6, "ricker": 7, "table": 8}
 FIELD = {"u": (0, 2), "j": (1, 2), "r": (2, 1), "pi": (3, 3), "h": (4, 4),
          "p": (5, 4), "s": (6, 2)}
 
@@ -61,6 +61,9 @@ def lib() -> C.CDLL:
         L.orc_set_listing_order.argtypes = [vp, i]
         L.orc_set_boundary_order.argtypes = [vp, i]
         L.orc_set_tau_plus.argtypes = [vp, d]
+        L.orc_set_corner.argtypes = [vp, i]
+        L.orc_set_side_table.restype = i
+        L.orc_set_side_table.argtypes = [vp, i, dp, i64]
         L.orc_collide_trt.argtypes = [d, dp, d, d, d, dp, dp, dp, dp, dp, dp]
         L.orc_set_side.restype = i
         L.orc_set_side.argtypes = [vp, i, i, i, d, d, d, d, d]
@@ -70,6 +73,9 @@ def lib() -> C.CDLL:
         L.orc_read.argtypes = [vp, i, dp]
         L.orc_read_f.argtypes = [vp, dp]
         L.orc_momentum.argtypes = [vp, dp]
+        L.orc_set_state.argtypes = [vp, dp, dp]
+        L.orc_get_prev.argtypes = [vp, dp, dp]
+        L.orc_set_prev.argtypes = [vp, dp, dp]
         L.orc_side_value.argtypes = [vp, i, i64, dp]
         L.orc_diag.argtypes = [vp, dp]
         L.orc_feq.argtypes = [d, dp, d, dp, dp, dp]
@@ -157,7 +163,7 @@ class Oracle:
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", rho0=1.0, dx=1.0,
                  body=(0.0, 0.0), threads=1, extrap="copy", order="text", boundary_order=1,
-                 tau_plus=None):
+                 tau_plus=None, corner=0):
         self.nx, self.ny = int(nx), int(ny)
         self._h = lib().orc_create(self.nx, self.ny, dx, rho0, mu, nu, tau,
                                    MATERIAL[material], body[0], body[1])
@@ -169,6 +175,9 @@ class Oracle:
         if boundary_order not in (1, 2):
             raise ValueError("boundary_order is 1 or 2")
         lib().orc_set_boundary_order(self._h, int(boundary_order))
+        if corner not in (0, 1, 2):
+            raise ValueError("corner is 0 (mean), 1 (x wall) or 2 (y wall)")
+        lib().orc_set_corner(self._h, int(corner))
         if tau_plus is not None:
             if not tau_plus > 0.5:
                 raise ValueError("tau_plus must exceed 0.5")
@@ -191,11 +200,15 @@ class Oracle:
     def n(self) -> int:
         return lib().orc_stepno(self._h)
 
-    def set_side(self, side, bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0):
+    def set_side(self, side, bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0, table=None):
         rc = lib().orc_set_side(self._h, SIDE[side], BC[bc], LOAD[kind], float(amp[0]),
                                 float(amp[1]), float(t0), float(t1), float(width))
         if rc != 0:
             raise ValueError(f"oracle rejected side {side}: {bc}/{kind}")
+        if kind == "table":
+            t = _f64(table).reshape(-1)
+            if lib().orc_set_side_table(self._h, SIDE[side], _p(t), t.size) != 0:
+                raise ValueError("a table program needs at least one entry")
 
     def init(self, u0=None, j0=None):
         N = self.nx * self.ny
@@ -218,6 +231,25 @@ class Oracle:
         out = np.zeros((9, self.ny, self.nx))
         lib().orc_read_f(self._h, _p(out))
         return out
+
+    def set_state(self, f=None, u=None):
+        """Set f(t_n) [9, ny, nx] and u_n [2, ny, nx] directly (None keeps one)."""
+        N = self.nx * self.ny
+        fa = None if f is None else _f64(f).reshape(9 * N)
+        ua = None if u is None else _f64(u).reshape(2 * N)
+        lib().orc_set_state(self._h, _p(fa) if fa is not None else None, _p(ua) if ua is not None else None)
+
+    def get_prev(self):
+        """The printed order's S_{n-1} [2, ny, nx] and T_{n-1} [4, ny, nx]."""
+        Sp, Tp = np.zeros((2, self.ny, self.nx)), np.zeros((4, self.ny, self.nx))
+        lib().orc_get_prev(self._h, _p(Sp), _p(Tp))
+        return Sp, Tp
+
+    def set_prev(self, Sp=None, Tp=None):
+        N = self.nx * self.ny
+        sa = None if Sp is None else _f64(Sp).reshape(2 * N)
+        ta = None if Tp is None else _f64(Tp).reshape(4 * N)
+        lib().orc_set_prev(self._h, _p(sa) if sa is not None else None, _p(ta) if ta is not None else None)
 
     def momentum(self) -> np.ndarray:
         out = np.zeros(2)

@@ -50,7 +50,7 @@
  *     wall's j* (the mean j* when it crosses two Dirichlet walls); a link that
  *     crosses one Neumann wall uses that wall's Pi_bd; the diagonal link that
  *     crosses two Neumann walls uses a combined Pi_bd (normal entries from
- *     each wall, shear entry the mean of both).
+ *     each wall, shear entry the mean of both, or as an option one wall's).
  *   - Initial state: f = f_eq(r0 = -rho0 tr H(u0), j0, Pi(H(u0))).
  *   - Collision: BGK (the paper's); two relaxation times as an option.
  * Periodic sides are an addition for tests (momentum balance, plane waves).
@@ -76,17 +76,19 @@ enum { SIDE_LEFT = 0, SIDE_RIGHT = 1, SIDE_BOTTOM = 2, SIDE_TOP = 3 };
 enum { BC_DIRICHLET = 0, BC_NEUMANN = 1, BC_PERIODIC = 2 };
 enum { MAT_SVK = 0, MAT_NH = 1, MAT_LINEAR = 2 };
 enum { LOAD_ZERO = 0, LOAD_CONST = 1, LOAD_DISP_RAMP = 2, LOAD_LINEAR_RAMP = 3,
-       LOAD_SIN2_RAMP = 4, LOAD_SIN_PULSE = 5, LOAD_GAUSS = 6, LOAD_RICKER = 7 };
+       LOAD_SIN2_RAMP = 4, LOAD_SIN_PULSE = 5, LOAD_GAUSS = 6, LOAD_RICKER = 7, LOAD_TABLE = 8 };
 enum { FIELD_U = 0, FIELD_J = 1, FIELD_R = 2, FIELD_PI = 3, FIELD_H = 4,
        FIELD_P = 5, FIELD_S = 6 };
 
 typedef struct {
     int bc, kind;
     double amp[2], t0, t1, width;
+    double *table;     /* LOAD_TABLE: the scalar program per step (owned copy) */
+    int64_t table_len;
 } side_t;
 
 typedef struct {
-    int nx, ny, material, extrap_linear, listing_order, boundary_order, threads;
+    int nx, ny, material, extrap_linear, listing_order, boundary_order, corner, threads;
     double dx, rho0, mu, nu, tau, body[2];
     /* derived, Sect. 3.2 */
     double lam, cs2, c, dt, omega;
@@ -289,6 +291,12 @@ static double load_g(const side_t *s, double n)
         double a = 2.0 / sqrt(3.0 * s->width * sqrt(M_PI));
         return a * (1.0 - d2 / s->width) * exp(-0.5 * d2 / s->width);
     }
+    case LOAD_TABLE: {
+        /* the sampled program, held at its last entry */
+        if (!s->table || s->table_len < 1) return 0.0;
+        int64_t k = (int64_t)n;
+        return s->table[k < s->table_len ? k : s->table_len - 1];
+    }
     default: return 0.0;
     }
 }
@@ -352,6 +360,7 @@ void orc_destroy(void *hv)
 {
     orc_t *h = (orc_t *)hv;
     if (!h) return;
+    for (int k = 0; k < 4; k++) free(h->side[k].table);
     free(h->f); free(h->fc); free(h->fn); free(h->u); free(h->un); free(h->jA);
     free(h->S); free(h->T); free(h->Sp); free(h->Tp); free(h->r); free(h->Pi);
     free(h);
@@ -370,6 +379,10 @@ void orc_set_listing_order(void *hv, int on) { ((orc_t *)hv)->listing_order = on
  * the CFL discussion of Sect. 3.2 would admit nu <= 5/11 (an option). */
 void orc_set_boundary_order(void *hv, int order) { ((orc_t *)hv)->boundary_order = order == 2 ? 2 : 1; }
 
+/* The shear entry of the Pi_bd of a link that crosses two Neumann walls: 0 the
+ * mean of the two walls' entries (default), 1 the x wall's, 2 the y wall's. */
+void orc_set_corner(void *hv, int mode) { ((orc_t *)hv)->corner = (mode == 1 || mode == 2) ? mode : 0; }
+
 /* tau_plus > 0.5: collide with two relaxation times (orc_collide_trt), the even
  * part at 1 / tau_plus; otherwise BGK. */
 void orc_set_tau_plus(void *hv, double tau_plus) { ((orc_t *)hv)->omega_plus = tau_plus > 0.5 ? 1.0 / tau_plus : 0.0; }
@@ -378,11 +391,24 @@ int orc_set_side(void *hv, int side, int bc, int kind, double ax, double ay,
                  double t0, double t1, double width)
 {
     orc_t *h = (orc_t *)hv;
-    if (side < 0 || side > 3 || bc < 0 || bc > 2 || kind < 0 || kind > 7) return -1;
+    if (side < 0 || side > 3 || bc < 0 || bc > 2 || kind < 0 || kind > 8) return -1;
     if (kind == LOAD_DISP_RAMP && bc != BC_DIRICHLET) return -1;
     side_t *s = &h->side[side];
     s->bc = bc; s->kind = kind; s->amp[0] = ax; s->amp[1] = ay;
     s->t0 = t0; s->t1 = t1; s->width = width;
+    return 0;
+}
+
+/* The sampled program of a TABLE side (copied; len >= 1). */
+int orc_set_side_table(void *hv, int side, const double *table, int64_t len)
+{
+    orc_t *h = (orc_t *)hv;
+    if (side < 0 || side > 3 || !table || len < 1) return -1;
+    side_t *s = &h->side[side];
+    free(s->table);
+    s->table = (double *)malloc((size_t)len * sizeof(double));
+    memcpy(s->table, table, (size_t)len * sizeof(double));
+    s->table_len = len;
     return 0;
 }
 
@@ -567,7 +593,8 @@ static void step_once(orc_t *h)
             double PiX[3] = {0, 0, 0}, PiY[3] = {0, 0, 0}, PiC[3];
             if (wx >= 0 && h->side[wx].bc == BC_NEUMANN) wall_Pi_bd(h, T, wx, x, y, n, PiX);
             if (wy >= 0 && h->side[wy].bc == BC_NEUMANN) wall_Pi_bd(h, T, wy, x, y, n, PiY);
-            PiC[0] = PiX[0]; PiC[2] = PiY[2]; PiC[1] = 0.5 * (PiX[1] + PiY[1]);
+            PiC[0] = PiX[0]; PiC[2] = PiY[2];
+            PiC[1] = h->corner == 1 ? PiX[1] : (h->corner == 2 ? PiY[1] : 0.5 * (PiX[1] + PiY[1]));
             for (int q = 1; q < 9; q++) {
                 int xt = x + EX[q], yt = y + EY[q];
                 int cx = !px && (xt < 0 || xt >= nx); /* crosses the x wall */
@@ -718,6 +745,35 @@ void orc_read_f(void *hv, double *out)
 {
     orc_t *h = (orc_t *)hv;
     memcpy(out, h->f, 9 * nn(h) * sizeof(double));
+}
+
+/* Set the state at the start of the current step directly: the pre-collision
+ * populations f(t_n) [9][ny][nx] and u_n [2][ny][nx] (either may be NULL to keep
+ * it).  For the linear analysis of the step (its matrix, column by column). */
+void orc_set_state(void *hv, const double *f, const double *u)
+{
+    orc_t *h = (orc_t *)hv;
+    size_t N = nn(h);
+    if (f) memcpy(h->f, f, 9 * N * sizeof(double));
+    if (u) memcpy(h->u, u, 2 * N * sizeof(double));
+}
+
+/* The printed order's extra state: S_{n-1} [2][ny][nx] and T_{n-1} [4][ny][nx]
+ * (read or set; NULL skips). */
+void orc_get_prev(void *hv, double *Sp, double *Tp)
+{
+    orc_t *h = (orc_t *)hv;
+    size_t N = nn(h);
+    if (Sp) memcpy(Sp, h->Sp, 2 * N * sizeof(double));
+    if (Tp) memcpy(Tp, h->Tp, 4 * N * sizeof(double));
+}
+
+void orc_set_prev(void *hv, const double *Sp, const double *Tp)
+{
+    orc_t *h = (orc_t *)hv;
+    size_t N = nn(h);
+    if (Sp) memcpy(h->Sp, Sp, 2 * N * sizeof(double));
+    if (Tp) memcpy(h->Tp, Tp, 4 * N * sizeof(double));
 }
 
 /* Total population momentum sum_X sum_q c_q f_q(t_n). */

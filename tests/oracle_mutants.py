@@ -83,6 +83,13 @@ MUT = [
  ("Ricker amplitude", "double a = 2.0 / sqrt(3.0 * s->width * sqrt(M_PI));", "double a = 1.0 / sqrt(3.0 * s->width * sqrt(M_PI));"),
  ("update without rho0", "h->un[i] = h->u[i] + dt / (2.0 * h->rho0) * (jx + h->jA[i]);", "h->un[i] = h->u[i] + dt / 2.0 * (jx + h->jA[i]);"),
  ("trapezoid uses new j twice", "h->un[N + i] = h->u[N + i] + dt / (2.0 * h->rho0) * (jy + h->jA[N + i]);", "h->un[N + i] = h->u[N + i] + dt / (2.0 * h->rho0) * (jy + jy);"),
+ ("diag kinetic energy without the half", "ek += (jx * jx + jy * jy) / (2.0 * h->rho0);", "ek += (jx * jx + jy * jy) / h->rho0;"),
+ ("diag max |u| squared", "out[3] = sqrt(mu2);", "out[3] = mu2;"),
+ ("diag flag ignores j", "if (!isfinite(jx) || !isfinite(jy) || !isfinite(ux)", "if (!isfinite(ux)"),
+ ("diag momentum y from j_x", "sx += jx; sy += jy;", "sx += jx; sy += jx;"),
+ ("diag |u| from u_x only", "double m = ux * ux + uy * uy;", "double m = ux * ux;"),
+ ("corner options swapped", "h->corner == 1 ? PiX[1] : (h->corner == 2 ? PiY[1]", "h->corner == 1 ? PiY[1] : (h->corner == 2 ? PiX[1]"),
+ ("table one step ahead", "return s->table[k < s->table_len ? k : s->table_len - 1];", "return s->table[k + 1 < s->table_len ? k + 1 : s->table_len - 1];"),
 ]
 TESTS = ["tests/test_oracle_blocks.py", "tests/test_oracle_invariants.py", "tests/test_paper_cases.py"]
 

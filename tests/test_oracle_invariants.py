@@ -97,6 +97,134 @@ def test_rigid_translation_between_moving_dirichlet_walls():
     np.testing.assert_allclose(o.read_f(), f0, atol=1e-15)
 
 
+# ---- diagnostics: closed forms ------------------------------------------------------
+
+def test_diagnostics_of_a_rigid_translation():
+    """The diagnostics (kinetic energy sum |j|^2 / (2 rho0), the largest |u|, the
+    sum of j and the non-finite flag; the quantities that watch for the
+    instabilities Sect. 4 and Sect. 6 report) on the free rigid translation,
+    where every node carries j = rho0 v0 and u_n = n dt v0: the kinetic energy is
+    N rho0 |v0|^2 / 2, the largest |u| is n dt |v0| and the momentum N rho0 v0."""
+    nx, ny, rho0 = 10, 8, 1.75
+    v0 = np.array([0.003, -0.0017])
+    o = make(nx, ny, {s: "neumann" for s in W.SIDES}, rho0=rho0)
+    j0 = np.zeros((2, ny, nx))
+    j0[0], j0[1] = rho0 * v0[0], rho0 * v0[1]
+    o.init(j0=j0)
+    n = 12
+    o.step(n)
+    d = o.diag()
+    N = nx * ny
+    assert d["ekin"] == pytest.approx(N * rho0 * float(v0 @ v0) / 2.0, rel=1e-13)
+    assert d["max_u"] == pytest.approx(n * o.dt * math.hypot(*v0), rel=1e-13)
+    np.testing.assert_allclose(d["momentum"], N * rho0 * v0, rtol=1e-13)
+    assert not d["nonfinite"]
+
+
+def test_diagnostics_of_a_homogeneous_start():
+    """At step 0 with u0 = H0 X (uniform gradient, so T is uniform and S = 0) and a
+    chosen j0, j equals j0: the kinetic energy is sum |j0|^2 / (2 rho0) for a j0
+    with a closed-form sum, and the largest |u| sits at the node farthest from the
+    origin, |H0 X| at X = ((nx - 1/2) dX, (ny - 1/2) dX)."""
+    nx, ny, rho0, dx = 9, 6, 0.8, 0.5
+    a, b = 0.01, -0.004
+    o = make(nx, ny, {s: "neumann" for s in W.SIDES}, rho0=rho0, dx=dx)
+    X, Y = nodes(nx, ny, dx)
+    u0 = np.stack([a * X, b * Y])
+    # j0 alternates +/- g along x on every row: sum |j0|^2 = N g^2 (x part) and
+    # the y part is the constant h
+    g, h = 2e-3, 5e-4
+    sign = np.where(np.arange(nx) % 2 == 0, 1.0, -1.0)
+    j0 = np.stack([np.broadcast_to(g * sign, (ny, nx)), np.full((ny, nx), h)])
+    o.init(u0, j0)
+    d = o.diag()
+    N = nx * ny
+    assert d["ekin"] == pytest.approx(N * (g * g + h * h) / (2.0 * rho0), rel=1e-12)
+    assert d["max_u"] == pytest.approx(math.hypot(a * (nx - 0.5) * dx, b * (ny - 0.5) * dx), rel=1e-13)
+    # alternating signs over an odd number of columns leave one column's worth
+    np.testing.assert_allclose(d["momentum"], [ny * g, N * h], rtol=1e-12)
+    assert not d["nonfinite"]
+
+
+@pytest.mark.parametrize("where", ["u", "j"])
+def test_diagnostics_flag_a_value_that_is_not_finite(where):
+    """One NaN in u0 or in j0 at one node raises the non-finite flag at step 0;
+    the same state without it does not."""
+    nx, ny = 7, 5
+    o = make(nx, ny, {s: "neumann" for s in W.SIDES})
+    u0 = W.random_field(nx, ny, 1e-4, 1)
+    j0 = W.random_field(nx, ny, 1e-4, 2)
+    o.init(u0, j0)
+    assert not o.diag()["nonfinite"]
+    bad = (u0 if where == "u" else j0).copy()
+    bad[1, 3, 4] = np.nan
+    o.init(bad, j0) if where == "u" else o.init(u0, bad)
+    assert o.diag()["nonfinite"]
+
+
+# ---- corner option and sampled load programs ----------------------------------------
+
+@pytest.mark.parametrize("mode, share", [(0, 0.5), (1, 1.0), (2, 0.0)])
+def test_corner_shear_entry_options(mode, share):
+    """A shear traction T*_y = t on the left wall only, from rest: after one step
+    the population entering the bottom-left corner node along (1, 1) comes from
+    the anti-bounce-back (Eq. abbcon) of the link that crosses both walls, with
+    Pi_bd holding only a shear entry.  That entry is the left wall's -s T*_y = t
+    (s = -1), the bottom wall's 0, or their mean, so the population is
+    2 w (2 Pi_xy c^2) / (2 c_s^4) = Pi_xy / (6 c_s^2) times 1, 0 or 1/2."""
+    t = 3e-4
+    o = make(6, 5, {"left": ("neumann", "const", (0.0, t)), "right": "neumann", "bottom": "neumann",
+                    "top": "neumann"}, corner=mode)
+    o.init()
+    o.step(1)
+    f = o.read_f()
+    cs2 = 0.05  # mu / rho0
+    assert f[5, 0, 0] == pytest.approx(share * t / (6.0 * cs2), rel=1e-13, abs=1e-300)
+
+
+def test_corner_options_are_mirror_images():
+    """Taking the shear entry from the x wall (option 1) or from the y wall
+    (option 2) are images of each other under the diagonal mirror x <-> y of a
+    square lattice with four free walls: a start and its mirror image stay
+    mirror images; the mean (option 0) is its own image."""
+    n = 12
+    u0 = W.smooth_field(n, n, 0.01, 8) + W.random_field(n, n, 1e-4, 9)
+    mirror = np.stack([u0[1].T, u0[0].T])
+    runs = {}
+    for mode, start in ((1, u0), (2, mirror), (0, u0), (0, mirror)):
+        o = make(n, n, {s: "neumann" for s in W.SIDES}, nu=0.2, corner=mode)
+        o.init(start)
+        o.step(60)
+        runs[(mode, start is u0)] = o.read("u")
+    a, b = runs[(1, True)], runs[(2, False)]
+    scale = np.abs(a).max()
+    np.testing.assert_allclose(b[0], a[1].T, atol=1e-12 * scale)
+    np.testing.assert_allclose(b[1], a[0].T, atol=1e-12 * scale)
+    c, d = runs[(0, True)], runs[(0, False)]
+    np.testing.assert_allclose(d[0], c[1].T, atol=1e-12 * scale)
+    assert np.abs(a - c).max() > 1e-9 * scale  # the option changes the corners' result
+
+
+def test_table_program_is_the_sampled_ramp():
+    """A TABLE program holding n / 16 for n = 0..16 (held at 1 after its end) is
+    the linear ramp over 16 steps, sample for sample: the runs agree bitwise."""
+    t1, amp = 16, (2e-4, -1e-4)
+    table = np.arange(t1 + 1) / t1
+    res = []
+    for spec in (("neumann", "linear_ramp", amp, 0.0, float(t1)), ("neumann", "table", amp)):
+        o = make(9, 7, {"left": "dirichlet", "right": spec, "bottom": "neumann", "top": "neumann"})
+        if spec[1] == "table":
+            o.set_side("right", "neumann", "table", amp, table=table)
+        o.init()
+        o.step(40)
+        res.append((o.read_f(), o.read("u")))
+        if spec[1] == "table":
+            assert o.side_value("right", 7)[0] == amp[0] * 7 / 16
+            assert o.side_value("right", 30)[1] == amp[1]
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    assert np.abs(res[0][1]).max() > 0
+
+
 def test_body_force_momentum_balance():
     """Periodic box with a body force b: the divergence of T sums to zero over a
     periodic lattice, so the total momentum sum_X sum_q c_q f_q grows by exactly
