@@ -47,8 +47,10 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     int pitch;
-    size_t f_bytes, u_bytes, part_bytes, out_bytes;
-    size_t off_f[2], off_u[2], off_part, off_out, total;
+    bool multipass;  // second-order boundary differences or the printed order
+    bool listing;    // the printed order: S and T of the previous level are state
+    size_t f_bytes, u_bytes, part_bytes, out_bytes, watch_bytes, t_bytes, s_bytes;
+    size_t off_f[2], off_u[2], off_part, off_out, off_watch, off_t[2], off_s[2], total;
 };
 
 // bytes per node of one population buffer: nine FP64 or FP32 values, or nine
@@ -66,6 +68,13 @@ Layout layout_of(const mclbm_params& p) {
     Geometry g{p.nx, p.ny, L.pitch, 0, 0, (long long)plane};
     L.part_bytes = align_up((size_t)diag_blocks(g) * 8 * sizeof(double));
     L.out_bytes = align_up(8 * sizeof(double));
+    L.watch_bytes = align_up(8 * sizeof(int64_t));
+    L.listing = p.time_levels == 1;
+    L.multipass = L.listing || p.boundary_order == 2;
+    // the multi-pass step holds T (4 components) and sigma (2) in FP64; the
+    // printed order keeps the previous level's beside the current one
+    L.t_bytes = L.multipass ? align_up(4 * plane * 8) : 0;
+    L.s_bytes = L.multipass ? align_up(2 * plane * 8) : 0;
     size_t o = 0;
     L.off_f[0] = o; o += L.f_bytes;
     L.off_f[1] = o; o += L.f_bytes;
@@ -73,6 +82,12 @@ Layout layout_of(const mclbm_params& p) {
     L.off_u[1] = o; o += L.u_bytes;
     L.off_part = o; o += L.part_bytes;
     L.off_out = o; o += L.out_bytes;
+    L.off_watch = o; o += L.watch_bytes;
+    for (int k = 0; k < 2; k++) {
+        L.off_t[k] = o; o += (k == 0 || L.listing) ? L.t_bytes : 0;
+        L.off_s[k] = o; o += (k == 0 || L.listing) ? L.s_bytes : 0;
+    }
+    if (!L.listing) { L.off_t[1] = L.off_t[0]; L.off_s[1] = L.off_s[0]; }
     L.total = o;
     return L;
 }
@@ -103,17 +118,33 @@ int check_params(const mclbm_params* p) {
         return fail(MCLBM_EINVAL, "unknown material %d", p->material);
     if (!std::isfinite(p->body[0]) || !std::isfinite(p->body[1]))
         return fail(MCLBM_EINVAL, "body force must be finite");
+    if (p->extrap != 0 && p->extrap != 1) return fail(MCLBM_EINVAL, "extrap must be 0 or 1 (got %d)", p->extrap);
+    if (p->corner < 0 || p->corner > 2) return fail(MCLBM_EINVAL, "corner must be 0, 1 or 2 (got %d)", p->corner);
+    if (p->boundary_order < 0 || p->boundary_order > 2)
+        return fail(MCLBM_EINVAL, "boundary_order must be 1 or 2 (0 means 1; got %d)", p->boundary_order);
+    if (p->time_levels != 0 && p->time_levels != 1)
+        return fail(MCLBM_EINVAL, "time_levels must be 0 or 1 (got %d)", p->time_levels);
+    if (p->diag_every < 0) return fail(MCLBM_EINVAL, "diag_every must be >= 0 (got %d)", p->diag_every);
+    if (p->reserved_ != 0) return fail(MCLBM_EINVAL, "reserved_ must be 0");
     return MCLBM_OK;
 }
 
 // lattice speed c = sqrt(3) c_s, c_s = sqrt(mu/rho0) (Sect. 3.2); dt = dX / c
 double lattice_speed(const mclbm_params& p) { return std::sqrt(3.0 * p.mu / p.rho0); }
 
+constexpr int64_t kMaxTable = (int64_t)1 << 26;
+
 int check_side(const mclbm_side_spec* s) {
     if (!s) return fail(MCLBM_EINVAL, "side spec is NULL");
     if (s->bc < MCLBM_DIRICHLET || s->bc > MCLBM_PERIODIC) return fail(MCLBM_EINVAL, "unknown wall type %d", s->bc);
-    if (s->kind < MCLBM_LOAD_ZERO || s->kind > MCLBM_LOAD_RICKER)
+    if (s->kind < MCLBM_LOAD_ZERO || s->kind > MCLBM_LOAD_TABLE)
         return fail(MCLBM_EINVAL, "unknown load program %d", s->kind);
+    if (s->kind == MCLBM_LOAD_TABLE) {
+        if (!s->table || s->table_len < 1 || s->table_len > kMaxTable)
+            return fail(MCLBM_EINVAL, "a TABLE program needs a table of 1..%lld entries", (long long)kMaxTable);
+        for (int64_t i = 0; i < s->table_len; i++)
+            if (!std::isfinite(s->table[i])) return fail(MCLBM_EINVAL, "TABLE entry %lld is not finite", (long long)i);
+    }
     if (s->kind == MCLBM_LOAD_DISP_RAMP && s->bc != MCLBM_DIRICHLET)
         return fail(MCLBM_EINVAL, "DISP_RAMP prescribes a wall speed and needs a Dirichlet side");
     const bool need_t1 = s->kind == MCLBM_LOAD_DISP_RAMP || s->kind == MCLBM_LOAD_LINEAR_RAMP ||
@@ -136,7 +167,9 @@ struct mclbm_sim {
     Coef k;
     double dt;
     mclbm_side_spec side[4];
+    std::vector<double> table[4];  // TABLE programs (side[i].table points here)
     int cur;       // which of the two population / displacement buffers is current
+    int sp;        // the printed order: which T / sigma buffer holds level n - 1
     int64_t n;     // steps since init
     bool inited;
 };
@@ -146,6 +179,10 @@ namespace {
 // Time program of a wall load at step n.
 double load_scale(const mclbm_side_spec& s, double n) {
     switch (s.kind) {
+    case MCLBM_LOAD_TABLE: {
+        const int64_t k = (int64_t)n;
+        return s.table[k < s.table_len ? k : s.table_len - 1];
+    }
     case MCLBM_LOAD_ZERO: return 0.0;
     case MCLBM_LOAD_CONST: return 1.0;
     case MCLBM_LOAD_LINEAR_RAMP: return n < s.t1 ? n / s.t1 : 1.0;
@@ -207,6 +244,7 @@ InitLike base_args(const mclbm_sim* s, const double* u) {
     b.lam = s->k.lam;
     b.mu = s->k.mu;
     b.rho0 = s->k.rho0;
+    b.bo = s->p.boundary_order == 2 ? 2 : 1;
     return b;
 }
 
@@ -226,13 +264,22 @@ int put_field2(mclbm_sim* s, double* dst, const double* src, int on_device) {
     return MCLBM_OK;
 }
 
+// the first-bad-step record of the diagnostics watch: -1, written by a small
+// host copy (ordered on the stream before any step)
+int reset_watch(mclbm_sim* s) {
+    static const int64_t none[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_watch), none, sizeof none, hipMemcpyHostToDevice, s->stream));
+    return MCLBM_OK;
+}
+
 }  // namespace
 
-MCLBM_EXPORT int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, double* dt_out) {
+MCLBM_EXPORT int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, size_t* align, double* dt_out) {
     const int rc = check_params(p);
     if (rc) return rc;
     const Layout L = layout_of(*p);
     if (arena_bytes) *arena_bytes = L.total;
+    if (align) *align = kAlign;
     if (dt_out) *dt_out = p->dx / lattice_speed(*p);
     return MCLBM_OK;
 }
@@ -275,12 +322,15 @@ MCLBM_EXPORT int mclbm_create(const mclbm_params* p, void* arena, size_t arena_b
     // its normal range
     s->k.fscale = p->precision == MCLBM_F16 ? std::ldexp(1.0, 12 - std::ilogb(p->rho0)) : 1.0;
     s->k.finv = 1.0 / s->k.fscale;
+    s->k.extrap = p->extrap;
+    s->k.corner = p->corner;
     for (int i = 0; i < 4; i++) {
         std::memset(&s->side[i], 0, sizeof(mclbm_side_spec));
         s->side[i].bc = MCLBM_NEUMANN;
         s->side[i].kind = MCLBM_LOAD_ZERO;
     }
     s->cur = 0;
+    s->sp = 0;
     s->n = 0;
     s->inited = false;
     *out = s;
@@ -295,6 +345,14 @@ MCLBM_EXPORT int mclbm_set_side(mclbm_sim* s, int side, const mclbm_side_spec* s
     if (s->inited && (spec->bc == MCLBM_PERIODIC) != (s->side[side].bc == MCLBM_PERIODIC))
         return fail(MCLBM_ESTATE, "periodicity of a side can only change before mclbm_init");
     s->side[side] = *spec;
+    if (spec->kind == MCLBM_LOAD_TABLE) {
+        s->table[side].assign(spec->table, spec->table + spec->table_len);
+        s->side[side].table = s->table[side].data();
+    } else {
+        s->table[side].clear();
+        s->side[side].table = nullptr;
+        s->side[side].table_len = 0;
+    }
     return MCLBM_OK;
 }
 
@@ -317,6 +375,15 @@ MCLBM_EXPORT int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, in
     a.inv_c = s->k.inv_c;
     a.fscale = s->k.fscale;
     HIP_TRY(launch_init(s->p.precision, a, s->stream));
+    s->sp = 0;
+    if (s->L.listing) {
+        // the printed order enters its first step with S and T of u0 as level -1
+        double* T = static_cast<double*>(at(s, s->L.off_t[0]));
+        double* sg = static_cast<double*>(at(s, s->L.off_s[0]));
+        HIP_TRY(launch_stress_pass(s->p.material, a.b, T, s->stream));
+        HIP_TRY(launch_source_pass(a.b, T, sg, s->stream));
+    }
+    if ((rc = reset_watch(s))) return rc;
     s->n = 0;
     s->inited = true;
     return MCLBM_OK;
@@ -343,14 +410,63 @@ int check_steppable(const mclbm_sim* s, int64_t nsteps) {
     return MCLBM_OK;
 }
 
+// arguments of the per-node read-out and diagnostics kernels at t_n
+ReadArgs read_args(const mclbm_sim* s) {
+    ReadArgs a;
+    a.b = base_args(s, static_cast<const double*>(at(s, s->L.off_u[s->cur])));
+    a.f = at(s, s->L.off_f[s->cur]);
+    a.dst = nullptr;
+    a.field = 0;
+    a.c0 = 0;
+    a.c1 = 4;
+    a.c = s->k.c;
+    a.s_from_sig = s->k.s_from_sig;
+    a.finv = s->k.finv;
+    a.partial = static_cast<double*>(at(s, s->L.off_part));
+    // the printed order's collision at t_n uses the held sigma of level n - 1
+    a.sig = s->L.listing ? static_cast<const double*>(at(s, s->L.off_s[s->sp])) : nullptr;
+    return a;
+}
+
+// one step on the stream: the fused launch, or the three passes of the
+// multi-pass step
+hipError_t launch_one_step(mclbm_sim* s) {
+    const StepArgs a = step_args(s);
+    if (!s->L.multipass) return launch_step(s->p.precision, s->p.material, a, s->stream);
+    PassArgs pa;
+    pa.s = a;
+    // level n goes to the buffers not holding level n - 1
+    const int wn = s->L.listing ? 1 - s->sp : 0;
+    pa.T = static_cast<double*>(at(s, s->L.off_t[wn]));
+    pa.sig = static_cast<double*>(at(s, s->L.off_s[wn]));
+    pa.Tw = static_cast<const double*>(at(s, s->L.off_t[s->L.listing ? s->sp : wn]));
+    pa.sig_c = static_cast<const double*>(at(s, s->L.off_s[s->L.listing ? s->sp : wn]));
+    const InitLike b = base_args(s, a.usrc);
+    hipError_t e = launch_stress_pass(s->p.material, b, pa.T, s->stream);
+    if (e == hipSuccess) e = launch_source_pass(b, pa.T, pa.sig, s->stream);
+    if (e == hipSuccess) e = launch_pass_step(s->p.precision, pa, s->stream);
+    return e;
+}
+
+void advance_one(mclbm_sim* s) {
+    s->cur = 1 - s->cur;
+    if (s->L.listing) s->sp = 1 - s->sp;
+    s->n++;
+}
+
 }  // namespace
 
 MCLBM_EXPORT int mclbm_step(mclbm_sim* s, int64_t nsteps) {
     if (int e = check_steppable(s, nsteps)) return e;
     for (int64_t i = 0; i < nsteps; i++) {
-        HIP_TRY(launch_step(s->p.precision, s->p.material, step_args(s), s->stream));
-        s->cur = 1 - s->cur;
-        s->n++;
+        HIP_TRY(launch_one_step(s));
+        advance_one(s);
+        if (s->p.diag_every > 0 && s->n % s->p.diag_every == 0) {
+            // the watch: diagnostics on the device, the first non-finite step kept
+            const ReadArgs a = read_args(s);
+            HIP_TRY(launch_diag(s->p.precision, s->p.material, a, static_cast<double*>(at(s, s->L.off_out)),
+                                static_cast<int64_t*>(at(s, s->L.off_watch)), s->n, s->stream));
+        }
     }
     return MCLBM_OK;
 }
@@ -360,6 +476,7 @@ MCLBM_EXPORT int mclbm_step_checked(mclbm_sim* s, int64_t nsteps, int64_t every,
     if (int e = check_steppable(s, nsteps)) return e;
     if (every < 1) return fail(MCLBM_EINVAL, "every must be >= 1");
     // the scan's table entry and its flag sit in the arena's diagnostics result area
+    // (the watch of diag_every writes there too, earlier on the same stream)
     char* area = static_cast<char*>(at(s, s->L.off_out));
     static_assert(sizeof(ScanEntry) + sizeof(uint32_t) <= 8 * sizeof(double), "result area too small");
     int64_t done = 0;
@@ -404,13 +521,12 @@ MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_s
     }
     for (int64_t i = 0; rc == MCLBM_OK && i < nsteps; i++) {
         hipError_t e = hipEventRecord(ev[i], s->stream);
-        if (e == hipSuccess) e = launch_step(s->p.precision, s->p.material, step_args(s), s->stream);
+        if (e == hipSuccess) e = launch_one_step(s);
         if (e != hipSuccess) {
             rc = fail(MCLBM_EHIP, "step launch failed: %s", hipGetErrorString(e));
             break;
         }
-        s->cur = 1 - s->cur;
-        s->n++;
+        advance_one(s);
     }
     if (rc == MCLBM_OK && hipEventRecord(ev[nsteps], s->stream) != hipSuccess)
         rc = fail(MCLBM_EHIP, "hipEventRecord failed");
@@ -478,6 +594,8 @@ void advance(mclbm_sim* s, int64_t k) {
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
+int check_side_program(const void* spec) { return check_side(static_cast<const mclbm_side_spec*>(spec)); }
+
 }  // namespace mclbm
 
 MCLBM_EXPORT int64_t mclbm_stepno(const mclbm_sim* s) { return s ? s->n : -1; }
@@ -498,19 +616,32 @@ MCLBM_EXPORT int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device)
     const int nc = mclbm_field_components(field);
     if (!nc) return fail(MCLBM_EINVAL, "unknown field %d", field);
     if (!dst) return fail(MCLBM_EINVAL, "dst is NULL");
-    ReadArgs a;
-    a.b = base_args(s, static_cast<const double*>(at(s, s->L.off_u[s->cur])));
-    a.f = at(s, s->L.off_f[s->cur]);
-    // a host destination is staged in the idle population buffer (>= 32 B per node)
-    a.dst = on_device ? dst : static_cast<double*>(at(s, s->L.off_f[1 - s->cur]));
+    ReadArgs a = read_args(s);
     a.field = field;
-    a.c = s->k.c;
-    a.s_from_sig = s->k.s_from_sig;
-    a.finv = s->k.finv;
     a.partial = nullptr;
-    HIP_TRY(launch_read(s->p.precision, s->p.material, a, s->stream));
-    const size_t bytes = (size_t)nc * s->g.nx * s->g.ny * sizeof(double);
-    if (!on_device) HIP_TRY(hipMemcpyAsync(dst, a.dst, bytes, hipMemcpyDeviceToHost, s->stream));
+    const size_t plane_out = (size_t)s->g.nx * s->g.ny;
+    if (on_device) {
+        a.dst = dst;
+        a.c0 = 0;
+        a.c1 = nc;
+        HIP_TRY(launch_read(s->p.precision, s->p.material, a, s->stream));
+    } else {
+        // a host destination is staged in the idle population buffer, as many
+        // components per pass as it holds (at least two: it has 18 B or more per
+        // node of the pitched lattice); each pass's copy is ordered before the
+        // next pass overwrites the staging
+        double* stage = static_cast<double*>(at(s, s->L.off_f[1 - s->cur]));
+        const int per = (int)std::min<size_t>((size_t)nc, s->L.f_bytes / (plane_out * sizeof(double)));
+        if (per < 1) return fail(MCLBM_EINVAL, "staging buffer too small");
+        for (int c0 = 0; c0 < nc; c0 += per) {
+            a.dst = stage;
+            a.c0 = c0;
+            a.c1 = std::min(nc, c0 + per);
+            HIP_TRY(launch_read(s->p.precision, s->p.material, a, s->stream));
+            HIP_TRY(hipMemcpyAsync(dst + (size_t)c0 * plane_out, stage, (size_t)(a.c1 - c0) * plane_out * sizeof(double),
+                                   hipMemcpyDeviceToHost, s->stream));
+        }
+    }
     HIP_TRY(hipStreamSynchronize(s->stream));
     return MCLBM_OK;
 }
@@ -519,29 +650,28 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
     if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
     if (!out) return fail(MCLBM_EINVAL, "out is NULL");
     if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_diag before mclbm_init");
-    ReadArgs a;
-    a.b = base_args(s, static_cast<const double*>(at(s, s->L.off_u[s->cur])));
-    a.f = at(s, s->L.off_f[s->cur]);
-    a.dst = nullptr;
-    a.field = 0;
-    a.c = s->k.c;
-    a.s_from_sig = s->k.s_from_sig;
-    a.finv = s->k.finv;
-    a.partial = static_cast<double*>(at(s, s->L.off_part));
+    const ReadArgs a = read_args(s);
     double* dout = static_cast<double*>(at(s, s->L.off_out));
-    HIP_TRY(launch_diag(s->p.precision, s->p.material, a, dout, s->stream));
+    HIP_TRY(launch_diag(s->p.precision, s->p.material, a, dout, nullptr, 0, s->stream));
     double h[5];
+    int64_t first_bad = -1;
     HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&first_bad, at(s, s->L.off_watch), sizeof first_bad, hipMemcpyDeviceToHost, s->stream));
     HIP_TRY(hipStreamSynchronize(s->stream));
+    std::memset(out, 0, sizeof *out);
     out->step = s->n;
+    out->first_bad_step = s->p.diag_every > 0 ? first_bad : -1;
     out->momentum[0] = h[0];
     out->momentum[1] = h[1];
     out->ekin = h[2];
     out->max_u = std::sqrt(h[3]);
     out->nonfinite = h[4] != 0.0;
     out->growth = s->p.growth_limit > 0.0 && out->max_u > s->p.growth_limit;
-    // c_d^2 = (lambda + 2 mu) / rho0 against c^2 = 3 mu / rho0
-    out->cfl_excess = 2.0 * s->p.mu * s->p.nu / (1.0 - 2.0 * s->p.nu) > s->p.mu;
+    // c_d^2 = (lambda + 2 mu) / rho0 against c^2 = 3 mu / rho0 (first-order
+    // boundary differences: c_d <= c, nu <= 1/4) or 4 c^2 (second order:
+    // c_d <= 2 c, nu <= 5/11)
+    const double lam = 2.0 * s->p.mu * s->p.nu / (1.0 - 2.0 * s->p.nu);
+    out->cfl_excess = s->p.boundary_order == 2 ? lam + 2.0 * s->p.mu > 12.0 * s->p.mu : lam > s->p.mu;
     if (out->nonfinite) return fail(MCLBM_EUNSTABLE, "non-finite u or j at step %lld", (long long)s->n);
     if (out->growth)
         return fail(MCLBM_EUNSTABLE, "max |u| %g above the growth limit %g at step %lld", out->max_u,
@@ -549,40 +679,108 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
     return MCLBM_OK;
 }
 
-MCLBM_EXPORT size_t mclbm_state_bytes(const mclbm_sim* s) {
-    return s ? s->L.f_bytes + s->L.u_bytes + sizeof(int64_t) : 0;
+namespace {
+
+// checkpoint header: 64 bytes ahead of the state
+struct CkptHeader {
+    char magic[8];      // "MCLBMCK1"
+    int32_t version;    // 1
+    int32_t nx, ny, precision, material, time_levels;
+    int64_t step;
+    uint64_t f_bytes, u_bytes, extra_bytes;  // populations, displacement, held level n - 1
+};
+static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
+constexpr char kMagic[8] = {'M', 'C', 'L', 'B', 'M', 'C', 'K', '1'};
+
+size_t extra_bytes(const mclbm_sim* s) { return s->L.listing ? s->L.t_bytes + s->L.s_bytes : 0; }
+
+CkptHeader header_of(const mclbm_sim* s) {
+    CkptHeader h;
+    std::memset(&h, 0, sizeof h);
+    std::memcpy(h.magic, kMagic, sizeof kMagic);
+    h.version = 1;
+    h.nx = s->p.nx;
+    h.ny = s->p.ny;
+    h.precision = s->p.precision;
+    h.material = s->p.material;
+    h.time_levels = s->p.time_levels;
+    h.step = s->n;
+    h.f_bytes = s->L.f_bytes;
+    h.u_bytes = s->L.u_bytes;
+    h.extra_bytes = extra_bytes(s);
+    return h;
 }
 
-MCLBM_EXPORT int mclbm_save(mclbm_sim* s, void* dst, int on_device) {
+}  // namespace
+
+MCLBM_EXPORT size_t mclbm_state_bytes(const mclbm_sim* s) {
+    return s ? sizeof(CkptHeader) + s->L.f_bytes + s->L.u_bytes + extra_bytes(s) : 0;
+}
+
+MCLBM_EXPORT int mclbm_save(mclbm_sim* s, void* dst, size_t dst_bytes, int on_device) {
     if (!s || !dst) return fail(MCLBM_EINVAL, "NULL argument");
     if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_save before mclbm_init");
+    if (dst_bytes < mclbm_state_bytes(s))
+        return fail(MCLBM_EINVAL, "checkpoint buffer has %zu bytes, %zu needed", dst_bytes, mclbm_state_bytes(s));
     char* d = static_cast<char*>(dst);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    HIP_TRY(hipMemcpyAsync(d, at(s, s->L.off_f[s->cur]), s->L.f_bytes, kind, s->stream));
-    HIP_TRY(hipMemcpyAsync(d + s->L.f_bytes, at(s, s->L.off_u[s->cur]), s->L.u_bytes, kind, s->stream));
+    const CkptHeader h = header_of(s);
+    size_t o = sizeof h;
+    HIP_TRY(hipMemcpyAsync(d + o, at(s, s->L.off_f[s->cur]), s->L.f_bytes, kind, s->stream));
+    o += s->L.f_bytes;
+    HIP_TRY(hipMemcpyAsync(d + o, at(s, s->L.off_u[s->cur]), s->L.u_bytes, kind, s->stream));
+    o += s->L.u_bytes;
+    if (s->L.listing) {
+        HIP_TRY(hipMemcpyAsync(d + o, at(s, s->L.off_t[s->sp]), s->L.t_bytes, kind, s->stream));
+        o += s->L.t_bytes;
+        HIP_TRY(hipMemcpyAsync(d + o, at(s, s->L.off_s[s->sp]), s->L.s_bytes, kind, s->stream));
+    }
     HIP_TRY(hipStreamSynchronize(s->stream));
-    const int64_t n = s->n;
-    if (on_device) HIP_TRY(hipMemcpy(d + s->L.f_bytes + s->L.u_bytes, &n, sizeof n, hipMemcpyHostToDevice));
-    else std::memcpy(d + s->L.f_bytes + s->L.u_bytes, &n, sizeof n);
+    if (on_device) HIP_TRY(hipMemcpy(d, &h, sizeof h, hipMemcpyHostToDevice));
+    else std::memcpy(d, &h, sizeof h);
     return MCLBM_OK;
 }
 
-MCLBM_EXPORT int mclbm_load(mclbm_sim* s, const void* src, int on_device) {
+MCLBM_EXPORT int mclbm_load(mclbm_sim* s, const void* src, size_t src_bytes, int on_device) {
     if (!s || !src) return fail(MCLBM_EINVAL, "NULL argument");
+    if (src_bytes < sizeof(CkptHeader)) return fail(MCLBM_EINVAL, "checkpoint of %zu bytes has no header", src_bytes);
     int rc = check_pairs(s);
     if (rc) return rc;
+    const char* d = static_cast<const char*>(src);
+    CkptHeader h;
+    if (on_device) HIP_TRY(hipMemcpy(&h, d, sizeof h, hipMemcpyDeviceToHost));
+    else std::memcpy(&h, d, sizeof h);
+    const CkptHeader want = header_of(s);
+    if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.version != 1)
+        return fail(MCLBM_EINVAL, "not an mclbm checkpoint (magic or version)");
+    if (h.nx != want.nx || h.ny != want.ny || h.precision != want.precision || h.material != want.material ||
+        h.time_levels != want.time_levels || h.f_bytes != want.f_bytes || h.u_bytes != want.u_bytes ||
+        h.extra_bytes != want.extra_bytes)
+        return fail(MCLBM_EINVAL,
+                    "checkpoint of a %d x %d lattice (precision %d, material %d, time levels %d) does not match "
+                    "this simulation (%d x %d, %d, %d, %d)", h.nx, h.ny, h.precision, h.material, h.time_levels,
+                    want.nx, want.ny, want.precision, want.material, want.time_levels);
+    if (h.step < 0) return fail(MCLBM_EINVAL, "checkpoint step counter is negative");
+    if (src_bytes < mclbm_state_bytes(s))
+        return fail(MCLBM_EINVAL, "checkpoint has %zu bytes, %zu needed", src_bytes, mclbm_state_bytes(s));
     s->g.px = s->side[MCLBM_LEFT].bc == MCLBM_PERIODIC;
     s->g.py = s->side[MCLBM_BOTTOM].bc == MCLBM_PERIODIC;
-    const char* d = static_cast<const char*>(src);
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     s->cur = 0;
-    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_f[0]), d, s->L.f_bytes, kind, s->stream));
-    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_u[0]), d + s->L.f_bytes, s->L.u_bytes, kind, s->stream));
-    int64_t n = 0;
-    if (on_device) HIP_TRY(hipMemcpy(&n, d + s->L.f_bytes + s->L.u_bytes, sizeof n, hipMemcpyDeviceToHost));
-    else std::memcpy(&n, d + s->L.f_bytes + s->L.u_bytes, sizeof n);
+    s->sp = 0;
+    size_t o = sizeof h;
+    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_f[0]), d + o, s->L.f_bytes, kind, s->stream));
+    o += s->L.f_bytes;
+    HIP_TRY(hipMemcpyAsync(at(s, s->L.off_u[0]), d + o, s->L.u_bytes, kind, s->stream));
+    o += s->L.u_bytes;
+    if (s->L.listing) {
+        HIP_TRY(hipMemcpyAsync(at(s, s->L.off_t[0]), d + o, s->L.t_bytes, kind, s->stream));
+        o += s->L.t_bytes;
+        HIP_TRY(hipMemcpyAsync(at(s, s->L.off_s[0]), d + o, s->L.s_bytes, kind, s->stream));
+    }
+    if ((rc = reset_watch(s))) return rc;
     HIP_TRY(hipStreamSynchronize(s->stream));
-    s->n = n;
+    s->n = h.step;
     s->inited = true;
     return MCLBM_OK;
 }

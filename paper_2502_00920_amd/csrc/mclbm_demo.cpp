@@ -47,7 +47,7 @@ int main(int argc, char** argv) {
 
     size_t bytes = 0;
     double dt = 0;
-    if (check(mclbm_plan(&p, &bytes, &dt), "mclbm_plan")) return 1;
+    if (check(mclbm_plan(&p, &bytes, nullptr, &dt), "mclbm_plan")) return 1;
     void* arena = nullptr;
     hipStream_t stream = nullptr;
     if (hipMalloc(&arena, bytes) != hipSuccess || hipStreamCreate(&stream) != hipSuccess) {

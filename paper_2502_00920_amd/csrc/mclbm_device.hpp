@@ -39,6 +39,8 @@ struct Coef {
     double lam, mu, rho0;
     double fscale;    // stored = population * fscale (a power of two; 1 except FP16 storage)
     double finv;      // 1 / fscale
+    int extrap;       // Neumann wall values: 0 the node's (zeroth order), 1 linear to the wall
+    int corner;       // shear entry of Pi_bd across two Neumann walls: 0 mean, 1 x wall's, 2 y wall's
 };
 
 // Wall data of one step: type per side and its value at t_n (j* for

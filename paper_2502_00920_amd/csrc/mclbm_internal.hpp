@@ -25,6 +25,7 @@ struct InitLike {
     const double* u;   // [2][ny][pitch]
     Geometry g;
     double inv_dx, inv_c2, sig_b[2], lam, mu, rho0;
+    int bo;            // one-sided differences at the outermost nodes: 1 or 2
 };
 
 struct InitArgs {
@@ -38,11 +39,25 @@ struct InitArgs {
 struct ReadArgs {
     InitLike b;
     const void* f;     // fc'_n
-    double* dst;       // [comp][ny][nx] FP64
+    double* dst;       // [comp - c0][ny][nx] FP64
     int field;
+    int c0, c1;        // components written: c0 <= comp < c1
     double c, s_from_sig;
     double finv;       // population = stored * finv
     double* partial;   // diagnostics: 8 doubles per block
+    const double* sig; // sigma of the collision at t_n when it is held (the
+                       // printed order's level n - 1), [2][ny][pitch]; else null
+};
+
+// The multi-pass step (second-order boundary differences, or the printed order
+// of the time levels): the stress pass writes T, the source pass sigma, and the
+// step kernel pulls, applies the walls, updates u and collides.
+struct PassArgs {
+    StepArgs s;
+    double* T;              // stress pass output: T_n [4][ny][pitch]
+    double* sig;            // source pass output: sigma_n [2][ny][pitch]
+    const double* Tw;       // stresses the walls of step n use (T_n, or T_{n-1})
+    const double* sig_c;    // sigma of the collision at t_n (sigma_n, or sigma_{n-1})
 };
 
 // One simulation's share of one step of a batch: its step arguments, its work
@@ -98,14 +113,23 @@ void advance(mclbm_sim* s, int64_t k);
 // the scan entry of s's displacement after k more steps
 void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e);
 int set_error(int code, const char* msg);
+// validation of a side program (the checks of mclbm_set_side)
+int check_side_program(const void* spec);
 
 // prec: PREC_F64 / F32 / F16 / BF16.  One launch: march_kernel over every node,
 // walls included.
 hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st);
+// the multi-pass step: stresses, source, step (three launches)
+hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st);
+hipError_t launch_source_pass(const InitLike& b, const double* T, double* sig, hipStream_t st);
+hipError_t launch_pass_step(int prec, const PassArgs& a, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t n4, hipStream_t st);
 hipError_t launch_init(int prec, const InitArgs& a, hipStream_t st);
 hipError_t launch_read(int prec, int material, const ReadArgs& a, hipStream_t st);
-hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, hipStream_t st);
+// diagnostics into out[0..4]; with watch non-null, also record step as the
+// first bad step in *watch when the values are not finite and *watch < 0
+hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
+                       hipStream_t st);
 int diag_blocks(const Geometry& g);
 
 }  // namespace mclbm

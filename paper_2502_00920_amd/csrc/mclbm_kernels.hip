@@ -172,6 +172,82 @@ __device__ __forceinline__ V from_prev(V v, V edge) { return dpp_shift<kDppWaveS
 template <typename V>
 __device__ __forceinline__ V from_next(V v, V edge) { return dpp_shift<kDppWaveShl1>(v, edge); }
 
+// ---- wall rules (Sect. 3.3), FP64 ----------------------------------------------------------
+//
+// The links of a wall node whose source lies beyond a wall, in FP64 in every
+// storage mode (the boundary-traction balance: T* and P(H) N nearly cancel on a
+// loaded wall), from the node's own post-collision populations fo (without the
+// forcing), its sigma (g0x, g0y) and its stresses td = P(H) + Pi(H) at t_n:
+// modified bounce-back (Eq. bbcon) across Dirichlet sides; modified
+// anti-bounce-back (Eq. abbcon) across Neumann sides, with Pi_bd N =
+// -T* + (P + Pi(H)) N in the wall's normal row and column and the population
+// moment Pi in the tangential entry, carried to the half-way wall at zeroth order
+// or, with k.extrap, linearly from the inward node (txx_i, tyx_i, myi: T_xx, T_yx
+// and the population Pi_yy / c^2 of the x wall's inward node; txy_i, tyy_i, mxi:
+// T_xy, T_yy and Pi_xx / c^2 of the y wall's).  A link crossing a Dirichlet and a Neumann
+// side takes the Dirichlet rule, one crossing two Dirichlet sides the mean of
+// their j*, one crossing two Neumann sides the Pi_bd with both normal rows from
+// the tractions and the shear entry by k.corner (the mean of the two walls' by
+// default).  atL / atR: the node is on the left / right wall (non-periodic x);
+// wyB / wyT: on the bottom / top wall.  Writes the incoming populations into fd.
+template <typename F>
+__device__ __forceinline__ void apply_walls(const Walls& W, const Coef& k, bool atL, bool atR, bool wyB, bool wyT,
+                                            const F fo[9], double g0x, double g0y, const double td[4],
+                                            double txx_i, double tyx_i, double myi, double txy_i, double tyy_i,
+                                            double mxi, double fd[9]) {
+    const double ic2 = k.inv_c2, icd = k.inv_c;
+    // r and the second moments: the collision keeps them and psi has neither
+    const double d5 = (double)fo[5] + (double)fo[7], d6 = (double)fo[6] + (double)fo[8];
+    const double a13 = (double)fo[1] + (double)fo[3], a24 = (double)fo[2] + (double)fo[4];
+    const double r0 = (double)fo[0] + a13 + a24 + (d5 + d6);
+    const double mxx = a13 + (d5 + d6);
+    const double myy = a24 + (d5 + d6);
+    const bool lin = k.extrap != 0;
+    auto ext = [&](double v, double vin) { return lin ? 0.5 * (3.0 * v - vin) : v; };
+    const bool wx = atL || atR, wy = wyB || wyT;
+    const int sx = atL ? SIDE_L : SIDE_R, sy = wyB ? SIDE_B : SIDE_T;
+    const double nxo = atL ? -1.0 : 1.0, nyo = wyB ? -1.0 : 1.0;  // outward normals
+    // Pi_bd / c^2 of each Neumann wall, (xx, xy, yy)
+    double PX[3] = {0.0, 0.0, 0.0}, PY[3] = {0.0, 0.0, 0.0};
+    if (wx && W.bc[sx] == BC_NEU) {
+        PX[0] = (-nxo * W.val[sx][0] + ext(td[0], txx_i)) * ic2;
+        PX[1] = (-nxo * W.val[sx][1] + ext(td[2], tyx_i)) * ic2;
+        PX[2] = ext(myy, myi);
+    }
+    if (wy && W.bc[sy] == BC_NEU) {
+        PY[0] = ext(mxx, mxi);
+        PY[1] = (-nyo * W.val[sy][0] + ext(td[1], txy_i)) * ic2;
+        PY[2] = (-nyo * W.val[sy][1] + ext(td[3], tyy_i)) * ic2;
+    }
+    const double PCxy = k.corner == 1 ? PX[1] : (k.corner == 2 ? PY[1] : 0.5 * (PX[1] + PY[1]));
+#pragma unroll
+    for (int q = 1; q < 9; q++) {
+        const int X = ex(q), Y = ey(q);
+        const bool cx = (atL && X < 0) || (atR && X > 0);  // the link leaves across the x wall
+        const bool cy = (wyB && Y < 0) || (wyT && Y > 0);  // ... across the y wall
+        if (!cx && !cy) continue;
+        const double w = wq<double>(q);
+        const double fcq = (double)fo[q] + 3.0 * w * (X * g0x + Y * g0y);  // post-collision with forcing
+        const bool dx_ = cx && W.bc[sx] == BC_DIR, dy_ = cy && W.bc[sy] == BC_DIR;
+        double val;
+        if (dx_ || dy_) {
+            double jx = 0.0, jy = 0.0;
+            if (dx_) { jx += W.val[sx][0] * icd; jy += W.val[sx][1] * icd; }
+            if (dy_) { jx += W.val[sy][0] * icd; jy += W.val[sy][1] * icd; }
+            const double kk = (dx_ && dy_) ? 0.5 : 1.0;
+            val = fcq - 6.0 * w * (X * jx + Y * jy) * kk;
+        } else {
+            const double Mxx = cx ? PX[0] : PY[0];
+            const double Myy = cy ? PY[2] : PX[2];
+            const double Mxy = (cx && cy) ? PCxy : (cx ? PX[1] : PY[1]);
+            const double eMe = X * X * Mxx + 2.0 * X * Y * Mxy + Y * Y * Myy;
+            const double e2 = X * X + Y * Y;
+            val = -fcq + 2.0 * w * (r0 + 0.5 * (9.0 * eMe - 3.0 * r0 * e2 - 3.0 * (Mxx + Myy) + 2.0 * r0));
+        }
+        fd[opp(q)] = val;
+    }
+}
+
 // ---- step: interior nodes, y-marching ------------------------------------------------------
 //
 // Each wave owns the 64 columns [x0, x0 + 64), x0 = 64 s, of a strip and marches
@@ -360,8 +436,9 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
 
         // T = P(H) + Pi(H) at row r of this lane; ul / ur: u of the columns left of
         // lane 0 and right of lane 63
-        auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], TS t[4],
+        auto stress = [&](int r, const double um[2], const double u0[2], const double up[2], auto* t,
                           const double ul[2], const double ur[2]) {
+            using TT = typename std::remove_pointer<decltype(t)>::type;  // TS, or double at walls
             double lx = from_prev(u0[0], ul[0]), rx = from_next(u0[0], ur[0]);
             double ly = from_prev(u0[1], ul[1]), ry = from_next(u0[1], ur[1]);
             double fx = 0.5 * idx, fy = 0.5 * idx;
@@ -379,32 +456,33 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 dy = hi ? u0[1] : dy;
                 fy = (lo || hi) ? idx : fy;
             }
-            excess_stress<TS, MAT>(TS((rx - lx) * fx), TS((dx - cx) * fy), TS((ry - ly) * fx),
-                                   TS((dy - cy) * fy), lam, mu, t);
+            excess_stress<TT, MAT>(TT((rx - lx) * fx), TT((dx - cx) * fy), TT((ry - ly) * fx),
+                                   TT((dy - cy) * fy), TT(a.k.lam), TT(a.k.mu), t);
         };
         // sigma = dt S / c at row r of this lane; tl / tr: T of the columns left of
         // lane 0 and right of lane 63
-        auto sigma = [&](int r, const TS tm[4], const TS t0[4], const TS tp[4], TS sg[2], const TS tl[4],
+        auto sigma = [&](int r, const auto* tm, const auto* t0, const auto* tp, TS sg[2], const TS tl[4],
                          const TS tr[4]) {
-            TS lxx = from_prev(t0[0], tl[0]), rxx = from_next(t0[0], tr[0]);
-            TS lyx = from_prev(t0[2], tl[2]), ryx = from_next(t0[2], tr[2]);
-            TS fx = TS(0.5), fy = TS(0.5);
-            TS cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3];
+            using TT = typename std::remove_cv<typename std::remove_pointer<decltype(t0)>::type>::type;
+            TT lxx = from_prev(t0[0], TT(tl[0])), rxx = from_next(t0[0], TT(tr[0]));
+            TT lyx = from_prev(t0[2], TT(tl[2])), ryx = from_next(t0[2], TT(tr[2]));
+            TT fx = TT(0.5), fy = TT(0.5);
+            TT cxy = tm[1], dxy = tp[1], cyy = tm[3], dyy = tp[3];
             if constexpr (EDGE) {
                 lxx = atL ? t0[0] : lxx;
                 lyx = atL ? t0[2] : lyx;
                 rxx = atR ? t0[0] : rxx;
                 ryx = atR ? t0[2] : ryx;
-                fx = (atL || atR) ? TS(1) : fx;
+                fx = (atL || atR) ? TT(1) : fx;
                 const bool lo = lo_row(r), hi = hi_row(r);
                 cxy = lo ? t0[1] : cxy;
                 cyy = lo ? t0[3] : cyy;
                 dxy = hi ? t0[1] : dxy;
                 dyy = hi ? t0[3] : dyy;
-                fy = (lo || hi) ? TS(1) : fy;
+                fy = (lo || hi) ? TT(1) : fy;
             }
-            sg[0] = ic2 * ((rxx - lxx) * fx + (dxy - cxy) * fy) + sbx;
-            sg[1] = ic2 * ((ryx - lyx) * fx + (dyy - cyy) * fy) + sby;
+            sg[0] = TS(TT(ic2) * ((rxx - lxx) * fx + (dxy - cxy) * fy) + TT(sbx));
+            sg[1] = TS(TT(ic2) * ((ryx - lyx) * fx + (dyy - cyy) * fy) + TT(sby));
         };
 
         // ---- halo: gathers (issued one block ahead) and the pass that fills the LDS
@@ -549,103 +627,6 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             wave_lds_sync();
         };
 
-        // The links of a wall node whose source lies beyond a wall (Sect. 3.3), from
-        // the node's own populations fo, sigma g0 and T t0 at t_n: modified
-        // bounce-back (Eq. bbcon) across Dirichlet sides, modified anti-bounce-back
-        // (Eq. abbcon) across Neumann sides.  A link crossing a Dirichlet and a
-        // Neumann side takes the Dirichlet rule, one crossing two Dirichlet sides
-        // the mean of their j*, one crossing two Neumann sides the Pi_bd with both
-        // normal rows from the tractions and the mean of the two shear entries.
-        const bool has_xwall = EDGE && !g.px && (x0 == 0 || (g.nx - 1 >= x0 && g.nx - 1 < x0 + 64));
-        const bool lane_xwall = has_xwall && xin && (atL || atR);
-        const T sxw = atL ? T(-1) : T(1);  // outward normal of this lane's x wall
-        // that wall's data (selects between kernel arguments, no indexing by lane)
-        const bool dirx = atL ? a.w.bc[SIDE_L] == BC_DIR : a.w.bc[SIDE_R] == BC_DIR;
-        const double vxw0 = atL ? a.w.val[SIDE_L][0] : a.w.val[SIDE_R][0];
-        const double vxw1 = atL ? a.w.val[SIDE_L][1] : a.w.val[SIDE_R][1];
-        const T jxw0 = T(vxw0 * a.k.inv_c), jxw1 = T(vxw1 * a.k.inv_c);  // j*/c
-        const T c2i = T(a.k.inv_c2);
-        const T kxx = -sxw * T(vxw0 * a.k.inv_c2), kxy = -sxw * T(vxw1 * a.k.inv_c2);  // -n T*/c^2
-        // the rule value for the outgoing link q = (X, Y) of weight w, with the
-        // incoming link's post-collision value fcq and the moments M/c^2 of the wall
-        auto abb = [&](T fcq, T w, T X, T Y, T r0, T Mxx, T Mxy, T Myy) {
-            const T eMe = X * X * Mxx + T(2) * X * Y * Mxy + Y * Y * Myy;
-            const T e2 = X * X + Y * Y;
-            return -fcq + T(2) * w * (r0 + T(0.5) * (T(9) * eMe - T(3) * r0 * e2 - T(3) * (Mxx + Myy) + T(2) * r0));
-        };
-        auto r0_m2 = [&](const T fo[9], T& r0, T& mxx, T& myy) {
-            r0 = T(0); mxx = T(0); myy = T(0);  // the collision keeps r and Pi; psi has neither
-#pragma unroll
-            for (int q = 0; q < 9; q++) {
-                r0 += fo[q];
-                if (ex(q)) mxx += fo[q];
-                if (ey(q)) myy += fo[q];
-            }
-        };
-        // links crossing only the x wall of this lane: p = (sx, 0), (sx, 1), (sx, -1),
-        // sx = -(outward normal); the outgoing link reflected is q = (-sx, -ey)
-        auto xwall_links = [&](const T fo[9], const TS g0s[2], const TS t0s[4], T f[9]) {
-            const T g0[2] = {T(g0s[0]), T(g0s[1])};
-            const T t0[4] = {T(t0s[0]), T(t0s[1]), T(t0s[2]), T(t0s[3])};
-            T r0, mxx, myy;
-            r0_m2(fo, r0, mxx, myy);
-            const T Mxx = kxx + t0[0] * c2i;
-            const T Mxy = kxy + t0[2] * c2i;
-            const T X = sxw;  // ex of the outgoing link
-            T v[3];
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                const T Y = k == 0 ? T(0) : (k == 1 ? T(-1) : T(1));  // ey of the outgoing link
-                const T w = k == 0 ? wq<T>(1) : wq<T>(5);
-                // q for the left wall: (-1, -ey) = 3, 7, 6; for the right wall: 1, 8, 5
-                const T foq = atL ? (k == 0 ? fo[3] : (k == 1 ? fo[7] : fo[6]))
-                                  : (k == 0 ? fo[1] : (k == 1 ? fo[8] : fo[5]));
-                const T fcq = foq + T(3) * w * (X * g0[0] + Y * g0[1]);
-                const T bb = fcq - T(6) * w * (X * jxw0 + Y * jxw1);
-                v[k] = dirx ? bb : abb(fcq, w, X, Y, r0, Mxx, Mxy, myy);
-            }
-            f[1] = atL ? v[0] : f[1];
-            f[5] = atL ? v[1] : f[5];
-            f[8] = atL ? v[2] : f[8];
-            f[3] = atR ? v[0] : f[3];
-            f[6] = atR ? v[1] : f[6];
-            f[7] = atR ? v[2] : f[7];
-        };
-        // links crossing the y wall of row 0 (onB) or ny-1, with the corner rules for
-        // those that cross an x wall too (wave-uniform: two rows per lattice)
-        auto ywall_links = [&](bool onB, const T fo[9], const TS g0s[2], const TS t0s[4], T f[9]) {
-            const T g0[2] = {T(g0s[0]), T(g0s[1])};
-            const T t0[4] = {T(t0s[0]), T(t0s[1]), T(t0s[2]), T(t0s[3])};
-            T r0, mxx, myy;
-            r0_m2(fo, r0, mxx, myy);
-            const T syw = onB ? T(-1) : T(1);
-            const bool diry = onB ? a.w.bc[SIDE_B] == BC_DIR : a.w.bc[SIDE_T] == BC_DIR;
-            const double vyw0 = onB ? a.w.val[SIDE_B][0] : a.w.val[SIDE_T][0];
-            const double vyw1 = onB ? a.w.val[SIDE_B][1] : a.w.val[SIDE_T][1];
-            const T Xxx = kxx + t0[0] * c2i;
-            const T Xxy = kxy + t0[2] * c2i;
-            const T Yyy = -syw * T(vyw1 * a.k.inv_c2) + t0[3] * c2i;
-            const T Yxy = -syw * T(vyw0 * a.k.inv_c2) + t0[1] * c2i;
-            const T jyw0 = T(vyw0 * a.k.inv_c), jyw1 = T(vyw1 * a.k.inv_c);
-#pragma unroll
-            for (int p = 1; p < 9; p++) {
-                if (ey(p) != (onB ? 1 : -1)) continue;  // links whose source is beyond the y wall
-                const bool crx = xin && ((atL && ex(p) > 0) || (atR && ex(p) < 0));
-                const int q = opp(p);
-                const T X = T(ex(q)), Y = T(ey(q)), w = wq<T>(q);
-                const T fcq = fo[q] + T(3) * w * (X * g0[0] + Y * g0[1]);
-                const bool dx_ = crx && dirx;
-                T jx = T(0), jy = T(0);
-                if (dx_) { jx += jxw0; jy += jxw1; }
-                if (diry) { jx += jyw0; jy += jyw1; }
-                const T bb = fcq - T(6) * w * (X * jx + Y * jy) / ((dx_ && diry) ? T(2) : T(1));
-                const T Mxx = crx ? Xxx : mxx;
-                const T Mxy = crx ? T(0.5) * (Xxy + Yxy) : Yxy;
-                const T ab = abb(fcq, w, X, Y, r0, Mxx, Mxy, Yyy);
-                f[p] = (dx_ || diry) ? bb : ab;
-            }
-        };
-
         // ---- the row pipeline
         double U0[2], U1[2], U2[2], tmp[2];
         TS T0[4], T1[4];
@@ -703,11 +684,6 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             f[3] = from_next(h[3], hR[0]);
             f[6] = from_next(h[6], hR[1]);
             f[7] = from_next(h[7], hR[2]);
-            if constexpr (EDGE) {
-                if (has_xwall && lane_xwall) xwall_links(F0, G0, T0, f);
-                if (!g.py && (r == 0 || r == g.ny - 1)) ywall_links(r == 0, F0, G0, T0, f);
-            }
-
             // Moments, equilibrium and relaxation in FP64 in every mode: the D2Q9
             // weights are not exact in FP32 (3 (2 w1 + 4 w5) rounds to 1 + 7.5e-9),
             // so an FP32 equilibrium scales j and Pi by about 1 + omega 7.5e-9 in
@@ -763,6 +739,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             stress(yc - 2, tmp, U0, U1, T0, l3, r3);
             stress(yc - 1, U0, U1, U2, T1, l4, r4);
         }
+
 #pragma unroll
         for (int q = 0; q < 9; q++) { Fm[q] = T(0); F0[q] = T(0); }
 
@@ -833,27 +810,37 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kerne
     }
 }
 
-// ---- per-node helpers for init, read-out and diagnostics (FP64, global loads) ----------
+// ---- per-node helpers for init, read-out, diagnostics and the multi-pass step (FP64) -------
 
 __device__ __forceinline__ double ld_u(const InitLike& a, int c, int gx, int gy) {
     return a.u[(size_t)c * a.g.plane + (size_t)gy * a.g.pitch + gx];
 }
 
+// Difference of a field along one axis at index m (0..n-1) of that axis, times
+// h (the spacing): central (v+ - v-) / 2 inside and across a periodic wrap;
+// at the outermost nodes of a non-periodic axis one-sided with the inward
+// neighbours, first order s (v1 - v0) or second order s (-3 v0 + 4 v1 - v2) / 2,
+// s = +1 at the low end, -1 at the high end (Sect. 3.2).  get(k) reads the
+// field at axis index k.
+template <typename Get>
+__device__ __forceinline__ double axis_diff(Get get, int m, int n, int per, int bo) {
+    if (per) return 0.5 * (get(wrap1(m + 1, n)) - get(wrap1(m - 1, n)));
+    if (m == 0 || m == n - 1) {
+        const int s = m == 0 ? 1 : -1;
+        if (bo == 2) return s * (-3.0 * get(m) + 4.0 * get(m + s) - get(m + 2 * s)) * 0.5;
+        return s * (get(m + s) - get(m));
+    }
+    return 0.5 * (get(m + 1) - get(m - 1));
+}
+
 // H = grad u at a node, (xx, xy, yx, yy)
 __device__ void node_H(const InitLike& a, int gx, int gy, double H[4]) {
     const Geometry& g = a.g;
-    int xl = gx - 1, xr = gx + 1, yl = gy - 1, yr = gy + 1;
-    double fx = 0.5 * a.inv_dx, fy = 0.5 * a.inv_dx;
-    if (g.px) { xl = wrap1(xl, g.nx); xr = wrap1(xr, g.nx); }
-    else if (gx == 0) { xl = gx; fx = a.inv_dx; }
-    else if (gx == g.nx - 1) { xr = gx; fx = a.inv_dx; }
-    if (g.py) { yl = wrap1(yl, g.ny); yr = wrap1(yr, g.ny); }
-    else if (gy == 0) { yl = gy; fy = a.inv_dx; }
-    else if (gy == g.ny - 1) { yr = gy; fy = a.inv_dx; }
-    H[0] = (ld_u(a, 0, xr, gy) - ld_u(a, 0, xl, gy)) * fx;
-    H[1] = (ld_u(a, 0, gx, yr) - ld_u(a, 0, gx, yl)) * fy;
-    H[2] = (ld_u(a, 1, xr, gy) - ld_u(a, 1, xl, gy)) * fx;
-    H[3] = (ld_u(a, 1, gx, yr) - ld_u(a, 1, gx, yl)) * fy;
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        H[2 * c] = axis_diff([&](int k) { return ld_u(a, c, k, gy); }, gx, g.nx, g.px, a.bo) * a.inv_dx;
+        H[2 * c + 1] = axis_diff([&](int k) { return ld_u(a, c, gx, k); }, gy, g.ny, g.py, a.bo) * a.inv_dx;
+    }
 }
 
 template <int MAT>
@@ -863,25 +850,23 @@ __device__ void node_T(const InitLike& a, int gx, int gy, double t[4]) {
     excess_stress<double, MAT>(H[0], H[1], H[2], H[3], a.lam, a.mu, t);
 }
 
-// sigma = dt S / c at a node
+// sigma = dt S / c at a node, from T at the nodes a get(x, y, t) supplies
+template <typename GetT>
+__device__ void sigma_from(const InitLike& a, int gx, int gy, GetT getT, double s[2]) {
+    const Geometry& g = a.g;
+    double d[2][2];  // d[row a][axis b] = dT_ab along b (times dX)
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+        d[r][0] = axis_diff([&](int k) { double t[4]; getT(k, gy, t); return t[2 * r]; }, gx, g.nx, g.px, a.bo);
+        d[r][1] = axis_diff([&](int k) { double t[4]; getT(gx, k, t); return t[2 * r + 1]; }, gy, g.ny, g.py, a.bo);
+    }
+    s[0] = a.inv_c2 * (d[0][0] + d[0][1]) + a.sig_b[0];
+    s[1] = a.inv_c2 * (d[1][0] + d[1][1]) + a.sig_b[1];
+}
+
 template <int MAT>
 __device__ void node_sigma(const InitLike& a, int gx, int gy, double s[2]) {
-    const Geometry& g = a.g;
-    int xl = gx - 1, xr = gx + 1, yl = gy - 1, yr = gy + 1;
-    double fx = 0.5, fy = 0.5;
-    if (g.px) { xl = wrap1(xl, g.nx); xr = wrap1(xr, g.nx); }
-    else if (gx == 0) { xl = gx; fx = 1.0; }
-    else if (gx == g.nx - 1) { xr = gx; fx = 1.0; }
-    if (g.py) { yl = wrap1(yl, g.ny); yr = wrap1(yr, g.ny); }
-    else if (gy == 0) { yl = gy; fy = 1.0; }
-    else if (gy == g.ny - 1) { yr = gy; fy = 1.0; }
-    double tl[4], tr[4], tb[4], tt[4];
-    node_T<MAT>(a, xl, gy, tl);
-    node_T<MAT>(a, xr, gy, tr);
-    node_T<MAT>(a, gx, yl, tb);
-    node_T<MAT>(a, gx, yr, tt);
-    s[0] = a.inv_c2 * ((tr[0] - tl[0]) * fx + (tt[1] - tb[1]) * fy) + a.sig_b[0];
-    s[1] = a.inv_c2 * ((tr[2] - tl[2]) * fx + (tt[3] - tb[3]) * fy) + a.sig_b[1];
+    sigma_from(a, gx, gy, [&](int x, int y, double t[4]) { node_T<MAT>(a, x, y, t); }, s);
 }
 
 // ---- init ------------------------------------------------------------------------------
@@ -912,6 +897,18 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
 
 // ---- read-out -----------------------------------------------------------------------------
 
+// sigma of the collision at t_n: held (the printed order's level n - 1) or from u_n
+template <int MAT>
+__device__ __forceinline__ void collision_sigma(const ReadArgs& a, int gx, int gy, double s[2]) {
+    if (a.sig) {
+        const size_t o = (size_t)gy * a.b.g.pitch + gx;
+        s[0] = a.sig[o];
+        s[1] = a.sig[(size_t)a.b.g.plane + o];
+    } else {
+        node_sigma<MAT>(a.b, gx, gy, s);
+    }
+}
+
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -922,21 +919,25 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     const size_t o = (size_t)gy * g.pitch + gx;
     const size_t oc = (size_t)gy * g.nx + gx, pc = (size_t)g.nx * g.ny;  // compact output
     double* d = a.dst;
+    // component c of the field goes to plane c - c0 when c0 <= c < c1
+    auto put = [&](int c, double v) {
+        if (c >= a.c0 && c < a.c1) d[(size_t)(c - a.c0) * pc + oc] = v;
+    };
     switch (a.field) {
     case 0:  // U
-        d[oc] = a.b.u[o];
-        d[pc + oc] = a.b.u[plane + o];
+        put(0, a.b.u[o]);
+        put(1, a.b.u[plane + o]);
         break;
     case 1: {  // J = c (M1' + sigma / 2)
         double s[2], mx = 0, my = 0;
-        node_sigma<MAT>(a.b, gx, gy, s);
+        collision_sigma<MAT>(a, gx, gy, s);
         for (int q = 0; q < 9; q++) {
             const double v = pop_get<PR>(a.f, plane, o, q, a.finv);
             mx += ex(q) * v;
             my += ey(q) * v;
         }
-        d[oc] = a.c * (mx + 0.5 * s[0]);
-        d[pc + oc] = a.c * (my + 0.5 * s[1]);
+        put(0, a.c * (mx + 0.5 * s[0]));
+        put(1, a.c * (my + 0.5 * s[1]));
         break;
     }
     case 2:  // R
@@ -950,12 +951,12 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
             pyy += ey(q) * ey(q) * v;
         }
         if (a.field == 2) {
-            d[oc] = r;
+            put(0, r);
         } else {
             const double c2 = a.c * a.c;
-            d[oc] = c2 * pxx;
-            d[pc + oc] = c2 * pxy;
-            d[2 * pc + oc] = c2 * pyy;
+            put(0, c2 * pxx);
+            put(1, c2 * pxy);
+            put(2, c2 * pyy);
         }
         break;
     }
@@ -964,21 +965,32 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
         double H[4], P[4];
         node_H(a.b, gx, gy, H);
         if (a.field == 5) first_pk<double, MAT>(H[0], H[1], H[2], H[3], a.b.lam, a.b.mu, P);
-        for (int c = 0; c < 4; c++) d[c * pc + oc] = a.field == 4 ? H[c] : P[c];
+        for (int c = 0; c < 4; c++) put(c, a.field == 4 ? H[c] : P[c]);
         break;
     }
-    case 6: {  // S
+    case 6: {  // S (from u_n)
         double s[2];
         node_sigma<MAT>(a.b, gx, gy, s);
-        d[oc] = s[0] * a.s_from_sig;
-        d[pc + oc] = s[1] * a.s_from_sig;
+        put(0, s[0] * a.s_from_sig);
+        put(1, s[1] * a.s_from_sig);
         break;
     }
     default: break;
     }
 }
 
-// ---- diagnostics: fixed-order block reductions ------------------------------------------------
+// ---- diagnostics: fixed-order reductions (wavefront lane shifts, then blocks) ----------------------
+
+// sum or max of v over the 64 lanes of this wave, in a fixed order (butterfly
+// through lane shuffles); every lane receives the result
+__device__ __forceinline__ double wave_reduce(double v, bool take_max) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = take_max ? fmax(v, o) : v + o;
+    }
+    return v;
+}
 
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
@@ -996,7 +1008,7 @@ __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
             mx += ex(q) * w;
             my += ey(q) * w;
         }
-        node_sigma<MAT>(a.b, gx, gy, s);
+        collision_sigma<MAT>(a, gx, gy, s);
         const double jx = a.c * (mx + 0.5 * s[0]), jy = a.c * (my + 0.5 * s[1]);
         const double ux = a.b.u[o], uy = a.b.u[plane + o];
         v[0] = a.c * mx;
@@ -1006,40 +1018,380 @@ __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
         v[4] = (isfinite(jx) && isfinite(jy) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
         if (v[4] != 0.0) v[3] = 0.0;
     }
-    __shared__ double red[5][256];
-    for (int c = 0; c < 5; c++) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            for (int c = 0; c < 5; c++) {
-                const double x = red[c][threadIdx.x], y = red[c][threadIdx.x + w];
-                red[c][threadIdx.x] = (c == 3 || c == 4) ? fmax(x, y) : x + y;
-            }
-        }
-        __syncthreads();
+    // each wave reduces its 64 nodes with lane shifts, then the block's four
+    // wave results are added in wave order
+    __shared__ double red[4][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+        const double r = wave_reduce(v[c], c >= 3);
+        if (lane == c) red[wv][c] = r;
     }
-    if (threadIdx.x < 5) a.partial[(size_t)blockIdx.x * 8 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int c = threadIdx.x;
+        double r = red[0][c];
+        for (int w = 1; w < 4; w++) r = (c >= 3) ? fmax(r, red[w][c]) : r + red[w][c];
+        a.partial[(size_t)blockIdx.x * 8 + c] = r;
+    }
 }
 
-__global__ __launch_bounds__(256) void diag_reduce_kernel(double* partial, int nblk, double* out) {
+// the block partials into out[0..4]; with watch set, lane 0 also records step in
+// watch[0] when the totals are not finite and watch[0] is still -1 (a vector
+// store from one lane)
+__global__ __launch_bounds__(256) void diag_reduce_kernel(const double* partial, int nblk, double* out,
+                                                          int64_t* watch, int64_t step) {
     double v[5] = {0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += 256)
         for (int c = 0; c < 5; c++) {
             const double x = partial[(size_t)b * 8 + c];
             v[c] = (c == 3 || c == 4) ? fmax(v[c], x) : v[c] + x;
         }
-    __shared__ double red[5][256];
-    for (int c = 0; c < 5; c++) red[c][threadIdx.x] = v[c];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int c = 0; c < 5; c++) {
-                const double x = red[c][threadIdx.x], y = red[c][threadIdx.x + w];
-                red[c][threadIdx.x] = (c == 3 || c == 4) ? fmax(x, y) : x + y;
-            }
-        __syncthreads();
+    __shared__ double red[4][5];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 5; c++) {
+        const double r = wave_reduce(v[c], c >= 3);
+        if (lane == c) red[wv][c] = r;
     }
-    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int c = threadIdx.x;
+        double r = red[0][c];
+        for (int w = 1; w < 4; w++) r = (c >= 3) ? fmax(r, red[w][c]) : r + red[w][c];
+        out[c] = r;
+        if (watch && c == 4 && r != 0.0 && watch[0] < 0) watch[0] = step;
+    }
+}
+
+// ---- the multi-pass step: second-order boundary differences, the printed time order -------
+//
+// Three launches per step, per node and in FP64 whatever the storage:
+//   1. stress pass: T_n = P(H) + Pi(H) from u_n (boundary differences of order bo)
+//   2. source pass: sigma_n = dt S_n / c from T_n (same differences)
+//   3. step: pull f(t_{n+1})_q = fc'_q(X - e_q) + dt psi_q(sigma_c(X - e_q)), the
+//      wall rules with the stresses Tw, u_{n+1} = u_n + dt/(2 rho0)(j_{n+1} + j_n)
+//      with j_n = c (M1(fc'_n) + sigma_c / 2) and j_{n+1} = c (M1(f) + sigma_n / 2),
+//      and the collision to fc'_{n+1}.
+// At the current level (Sect. 3.1) sigma_c = sigma_n and Tw = T_n; in the order
+// printed in Algorithm 1 they are the held sigma_{n-1} and T_{n-1}.
+
+template <int MAT>
+__global__ __launch_bounds__(256) void stress_pass_kernel(InitLike b, double* T) {
+    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (gx >= b.g.nx || gy >= b.g.ny) return;
+    const size_t plane = (size_t)b.g.plane, o = (size_t)gy * b.g.pitch + gx;
+    double t[4];
+    node_T<MAT>(b, gx, gy, t);
+#pragma unroll
+    for (int c = 0; c < 4; c++) T[(size_t)c * plane + o] = t[c];
+}
+
+__global__ __launch_bounds__(256) void source_pass_kernel(InitLike b, const double* __restrict__ T,
+                                                          double* __restrict__ sig) {
+    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (gx >= b.g.nx || gy >= b.g.ny) return;
+    const size_t plane = (size_t)b.g.plane, o = (size_t)gy * b.g.pitch + gx;
+    double s[2];
+    sigma_from(b, gx, gy,
+               [&](int x, int y, double t[4]) {
+                   const size_t oo = (size_t)y * b.g.pitch + x;
+#pragma unroll
+                   for (int c = 0; c < 4; c++) t[c] = T[(size_t)c * plane + oo];
+               },
+               s);
+    sig[o] = s[0];
+    sig[plane + o] = s[1];
+}
+
+// The displacement and constants of a step, for the per-node helpers.
+__device__ __forceinline__ InitLike init_like(const StepArgs& a, int bo) {
+    InitLike b;
+    b.u = a.usrc;
+    b.g = a.g;
+    b.inv_dx = a.k.inv_dx;
+    b.inv_c2 = a.k.inv_c2;
+    b.sig_b[0] = a.k.sig_b[0];
+    b.sig_b[1] = a.k.sig_b[1];
+    b.lam = a.k.lam;
+    b.mu = a.k.mu;
+    b.rho0 = a.k.rho0;
+    b.bo = bo;
+    return b;
+}
+
+// The whole update of one node in FP64, walls included: pull
+// f(t_{n+1})_q = fc'_q(X - e_q) + dt psi_q(sigma_c(X - e_q)), the wall rules
+// (apply_walls) with the stresses Tw, u_{n+1} = u_n + dt/(2 rho0)(j_{n+1} + j_n)
+// with j_n = c (M1(fc'_n) + sigma_c / 2) and j_{n+1} = c (M1(f) + sigma_n / 2),
+// and the collision to fc'_{n+1}.  sig_c(x, y, s): sigma of the collision at
+// t_n at a node; sig_n(s): sigma_n at this node; Tw(x, y, t): the stresses the
+// walls use.
+template <int PR, bool TWO_RATES, typename SigC, typename SigN, typename TW>
+__device__ __forceinline__ void node_update(const StepArgs& a, int gx, int gy, SigC sig_c, SigN sig_n, TW Tw) {
+    const Geometry& g = a.g;
+    const size_t plane = (size_t)g.plane;
+    const size_t o = (size_t)gy * g.pitch + gx;
+    const double finv = a.k.finv;
+    double fo[9], f[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) fo[q] = pop_get<PR>(a.fsrc, plane, o, q, finv);
+    // pulls with the forcing of the collision at the source node
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        int sx = gx - ex(q), sy = gy - ey(q);
+        if (g.px) sx = wrap1(sx, g.nx);
+        if (g.py) sy = wrap1(sy, g.ny);
+        f[q] = 0.0;  // links from beyond a wall: the wall rules below
+        if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny) continue;
+        double sg[2];
+        sig_c(sx, sy, sg);
+        f[q] = pop_get<PR>(a.fsrc, plane, (size_t)sy * g.pitch + sx, q, finv) +
+               3.0 * wq<double>(q) * (ex(q) * sg[0] + ey(q) * sg[1]);
+    }
+    const bool atL = !g.px && gx == 0, atR = !g.px && gx == g.nx - 1;
+    const bool wyB = !g.py && gy == 0, wyT = !g.py && gy == g.ny - 1;
+    double sc[2];
+    sig_c(gx, gy, sc);
+    if (atL || atR || wyB || wyT) {
+        double td[4], txi[4] = {0.0, 0.0, 0.0, 0.0}, tyi[4] = {0.0, 0.0, 0.0, 0.0}, myi = 0.0, mxi = 0.0;
+        Tw(gx, gy, td);
+        if (a.k.extrap) {
+            if (atL || atR) {  // the x wall's inward node
+                const int xi = atL ? gx + 1 : gx - 1;
+                Tw(xi, gy, txi);
+                const size_t oi = (size_t)gy * g.pitch + xi;
+#pragma unroll
+                for (int q = 2; q < 9; q++)
+                    if (ey(q) != 0) myi += pop_get<PR>(a.fsrc, plane, oi, q, finv);
+            }
+            if (wyB || wyT) {  // the y wall's inward node
+                const int yi = wyB ? gy + 1 : gy - 1;
+                Tw(gx, yi, tyi);
+                const size_t oi = (size_t)yi * g.pitch + gx;
+#pragma unroll
+                for (int q = 1; q < 9; q++)
+                    if (ex(q) != 0) mxi += pop_get<PR>(a.fsrc, plane, oi, q, finv);
+            }
+        }
+        apply_walls(a.w, a.k, atL, atR, wyB, wyT, fo, sc[0], sc[1], td, txi[0], txi[2], myi, tyi[1], tyi[3], mxi, f);
+    }
+    // moments and the trapezoidal displacement update
+    double m1x = 0.0, m1y = 0.0, o1x = 0.0, o1y = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        m1x += ex(q) * f[q];
+        m1y += ey(q) * f[q];
+        o1x += ex(q) * fo[q];
+        o1y += ey(q) * fo[q];
+    }
+    double sn[2];
+    sig_n(sn);
+    a.udst[o] = a.usrc[o] + a.k.ucoef * (m1x + o1x + 0.5 * (sn[0] + sc[0]));
+    a.udst[plane + o] = a.usrc[plane + o] + a.k.ucoef * (m1y + o1y + 0.5 * (sn[1] + sc[1]));
+    double fn[9];
+    collide_node<TWO_RATES>(f, collide_rates(a.k.omega, a.k.omega_p), fn);
+    pop_put_all<PR>(a.fdst, plane, o, fn, a.k.fscale);
+}
+
+template <int PR, bool TWO_RATES>
+__global__ __launch_bounds__(256) void pass_step_kernel(PassArgs pa) {
+    const StepArgs& a = pa.s;
+    const Geometry& g = a.g;
+    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (gx >= g.nx || gy >= g.ny) return;
+    const size_t plane = (size_t)g.plane;
+    auto sig_c = [&](int x, int y, double s[2]) {
+        const size_t oo = (size_t)y * g.pitch + x;
+        s[0] = pa.sig_c[oo];
+        s[1] = pa.sig_c[plane + oo];
+    };
+    auto sig_n = [&](double s[2]) {
+        const size_t oo = (size_t)gy * g.pitch + gx;
+        s[0] = pa.sig[oo];
+        s[1] = pa.sig[plane + oo];
+    };
+    auto Tw = [&](int x, int y, double t[4]) {
+        const size_t oo = (size_t)y * g.pitch + x;
+#pragma unroll
+        for (int c = 0; c < 4; c++) t[c] = pa.Tw[(size_t)c * plane + oo];
+    };
+    node_update<PR, TWO_RATES>(a, gx, gy, sig_c, sig_n, Tw);
+}
+
+// ---- the wall pass of the fused step ------------------------------------------------------
+//
+// march_kernel leaves the nodes on non-periodic sides with pulls from beyond the
+// wall; this pass redoes their whole update in FP64 (node_update: the walls of
+// Sect. 3.3 with T and sigma of u_n, first-order boundary differences), after
+// march_kernel on the same stream.  A block takes a segment of kWallSeg nodes of
+// one side (the rows 0 and ny - 1 of non-periodic y sides whole, the columns 0
+// and nx - 1 of non-periodic x sides between them): it computes T on the three
+// node lines nearest the wall and sigma on the two nearest into LDS, then one
+// thread per wall node updates it from those.
+
+constexpr int kWallSeg = 256;
+struct WallBand {
+    double T[3][kWallSeg + 4][4];  // [distance from the wall][along, from start - 2][comp]
+    double S[2][kWallSeg + 2][2];  // [distance][along, from start - 1][comp]
+};
+
+struct WallSegs {
+    int nrow, ncol;  // segments per row side, per column side
+    int total;
+};
+__host__ __device__ __forceinline__ WallSegs wall_segs(const Geometry& g) {
+    WallSegs w;
+    w.nrow = g.py ? 0 : (g.nx + kWallSeg - 1) / kWallSeg;
+    const int h = g.py ? g.ny : g.ny - 2;
+    w.ncol = g.px ? 0 : (h + kWallSeg - 1) / kWallSeg;
+    w.total = 2 * w.nrow + 2 * w.ncol;
+    return w;
+}
+
+template <int PR, int MAT>
+__device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
+    const Geometry& g = a.g;
+    const WallSegs ws = wall_segs(g);
+    // side: 0 bottom row, 1 top row, 2 left column, 3 right column
+    int side, start;
+    if (seg < 2 * ws.nrow) {
+        side = seg / ws.nrow;
+        start = (seg % ws.nrow) * kWallSeg;
+    } else {
+        const int k = seg - 2 * ws.nrow;
+        side = 2 + k / ws.ncol;
+        start = (g.py ? 0 : 1) + (k % ws.ncol) * kWallSeg;
+    }
+    const bool rowside = side < 2;
+    const int len = rowside ? g.nx : g.ny;                        // nodes along the wall
+    const int per = rowside ? g.px : g.py;                        // periodic along it
+    const int end = rowside ? g.nx : (g.py ? g.ny : g.ny - 1);    // wall nodes of this side: [.., end)
+    // node (x, y) at along-wall index t and distance d from the wall
+    auto node = [&](int t, int d, int* x, int* y) {
+        if (rowside) { *x = t; *y = side == 0 ? d : g.ny - 1 - d; }
+        else { *y = t; *x = side == 2 ? d : g.nx - 1 - d; }
+    };
+    auto along = [&](int t, bool* ok) {  // an along-wall index into the lattice, wrapped if periodic
+        if (per) return wrap(t, len);
+        *ok = *ok && t >= 0 && t < len;
+        return t;
+    };
+    const InitLike b = init_like(a, 1);
+    // T on the three nearest lines, from u_n
+    for (int k = threadIdx.x; k < 3 * (kWallSeg + 4); k += blockDim.x) {
+        const int d = k / (kWallSeg + 4), i = k % (kWallSeg + 4);
+        bool ok = true;
+        const int t = along(start - 2 + i, &ok);
+        if (!ok) continue;
+        int x, y;
+        node(t, d, &x, &y);
+        node_T<MAT>(b, x, y, band.T[d][i]);
+    }
+    __syncthreads();
+    // band entries of a node (x, y) near the segment: its distance from the wall
+    // and its along-wall index relative to the band's first (periodic: the
+    // representative in range; band entries of the same node hold the same values)
+    auto dist = [&](int x, int y) {
+        return rowside ? (side == 0 ? y : g.ny - 1 - y) : (side == 2 ? x : g.nx - 1 - x);
+    };
+    auto rel = [&](int x, int y, int first) {
+        const int i = (rowside ? x : y) - first;
+        return per ? wrap(i, len) : i;
+    };
+    auto Tband = [&](int x, int y, double t[4]) {
+        const int dd = dist(x, y), i = rel(x, y, start - 2);
+#pragma unroll
+        for (int c = 0; c < 4; c++) t[c] = band.T[dd][i][c];
+    };
+    // sigma on the two nearest lines, from that T
+    for (int k = threadIdx.x; k < 2 * (kWallSeg + 2); k += blockDim.x) {
+        const int d = k / (kWallSeg + 2), i = k % (kWallSeg + 2);
+        bool ok = true;
+        const int t = along(start - 1 + i, &ok);
+        if (!ok) continue;
+        int x, y;
+        node(t, d, &x, &y);
+        sigma_from(b, x, y, Tband, band.S[d][i]);
+    }
+    __syncthreads();
+    // the wall nodes
+    const int t = start + (int)threadIdx.x;
+    if ((int)threadIdx.x >= kWallSeg || t >= end) return;
+    int gx, gy;
+    node(t, 0, &gx, &gy);
+    auto Sband = [&](int x, int y, double s[2]) {
+        const int dd = dist(x, y), i = rel(x, y, start - 1);
+        s[0] = band.S[dd][i][0];
+        s[1] = band.S[dd][i][1];
+    };
+    auto sig_n = [&](double s[2]) { Sband(gx, gy, s); };
+    if (a.k.omega_p != a.k.omega) node_update<PR, true>(a, gx, gy, Sband, sig_n, Tband);
+    else node_update<PR, false>(a, gx, gy, Sband, sig_n, Tband);
+}
+
+template <int PR, int MAT>
+__global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
+    __shared__ WallBand band;
+    wall_segment<PR, MAT>(a, blockIdx.x, band);
+}
+
+// the wall pass of every simulation in a batch table, on a fixed grid: block b
+// takes the segments b, b + grid, ... of the table's simulations in order
+constexpr int kWallBatchBlocks = 256;
+template <int PR, int MAT>
+__global__ __launch_bounds__(256) void wall_batch_kernel(const BatchStep* __restrict__ step) {
+    __shared__ WallBand band;
+    const int nsims = step->nsims;
+    int base = 0;  // segments of the simulations before s
+    for (int s = 0; s < nsims; s++) {
+        const BatchEntry& e = step->e[s];
+        const int n = e.skip ? 0 : wall_segs(e.a.g).total;
+        // the first of this block's segments at or after base
+        int k = (int)blockIdx.x - base % (int)gridDim.x;
+        if (k < 0) k += gridDim.x;
+        for (; k < n; k += gridDim.x) {
+            wall_segment<PR, MAT>(e.a, k, band);
+            __syncthreads();  // the band is reused by the next segment
+        }
+        base += n;
+    }
+}
+
+hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st) {
+    const dim3 grid((b.g.nx + 63) / 64, (b.g.ny + 3) / 4), block(256);
+    switch (material) {
+    case MAT_SVK: hipLaunchKernelGGL((stress_pass_kernel<MAT_SVK>), grid, block, 0, st, b, T); break;
+    case MAT_NH: hipLaunchKernelGGL((stress_pass_kernel<MAT_NH>), grid, block, 0, st, b, T); break;
+    default: hipLaunchKernelGGL((stress_pass_kernel<MAT_LIN>), grid, block, 0, st, b, T); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_source_pass(const InitLike& b, const double* T, double* sig, hipStream_t st) {
+    const dim3 grid((b.g.nx + 63) / 64, (b.g.ny + 3) / 4), block(256);
+    hipLaunchKernelGGL(source_pass_kernel, grid, block, 0, st, b, T, sig);
+    return hipGetLastError();
+}
+
+template <int PR>
+static void pass_step_p(const PassArgs& a, hipStream_t st) {
+    const dim3 grid((a.s.g.nx + 63) / 64, (a.s.g.ny + 3) / 4), block(256);
+    if (a.s.k.omega_p != a.s.k.omega) hipLaunchKernelGGL((pass_step_kernel<PR, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((pass_step_kernel<PR, false>), grid, block, 0, st, a);
+}
+
+hipError_t launch_pass_step(int prec, const PassArgs& a, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: pass_step_p<PREC_F64>(a, st); break;
+    case PREC_F32: pass_step_p<PREC_F32>(a, st); break;
+    case PREC_F16: pass_step_p<PREC_F16>(a, st); break;
+    default: pass_step_p<PREC_BF16>(a, st); break;
+    }
+    return hipGetLastError();
 }
 
 // Failure scan: every node of every listed lattice, both displacement components;
@@ -1119,37 +1471,44 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
     *nchunk = (g.ny + *chunk - 1) / *chunk;
 }
 
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st) {
-    const dim3 block(256);
-    if (prec == PREC_F64) {
-        const dim3 grid(batch_blocks<PREC_F64>());
-        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        else hipLaunchKernelGGL((march_batch_kernel<PREC_F64, MAT_NH, 6, 2>), grid, block, 0, st, step);
-    } else if (prec == PREC_F32) {
-        const dim3 grid(batch_blocks<PREC_F32>());
-        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        else hipLaunchKernelGGL((march_batch_kernel<PREC_F32, MAT_NH, 6, 2>), grid, block, 0, st, step);
-    } else if (prec == PREC_F16) {
-        const dim3 grid(batch_blocks<PREC_F16>());
-        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_F16, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        else hipLaunchKernelGGL((march_batch_kernel<PREC_F16, MAT_NH, 6, 2>), grid, block, 0, st, step);
+template <int PR>
+static void batch_step_p(int material, const BatchStep* step, hipStream_t st) {
+    const dim3 grid(batch_blocks<PR>()), wgrid(kWallBatchBlocks), block(256);
+    if (material == MAT_SVK) {
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
     } else {
-        const dim3 grid(batch_blocks<PREC_BF16>());
-        if (material == MAT_SVK) hipLaunchKernelGGL((march_batch_kernel<PREC_BF16, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        else hipLaunchKernelGGL((march_batch_kernel<PREC_BF16, MAT_NH, 6, 2>), grid, block, 0, st, step);
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), grid, block, 0, st, step);
+        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_NH>), wgrid, block, 0, st, step);
+    }
+}
+
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: batch_step_p<PREC_F64>(material, step, st); break;
+    case PREC_F32: batch_step_p<PREC_F32>(material, step, st); break;
+    case PREC_F16: batch_step_p<PREC_F16>(material, step, st); break;
+    default: batch_step_p<PREC_BF16>(material, step, st); break;
     }
     return hipGetLastError();
+}
+
+template <int PR, int MAT>
+static void launch_march_and_walls(const StepArgs& a, hipStream_t st) {
+    launch_march<PR, MAT, 6, 2>(a, st);
+    const int nseg = wall_segs(a.g).total;
+    if (nseg > 0) hipLaunchKernelGGL((wall_kernel<PR, MAT>), dim3(nseg), dim3(256), 0, st, a);
 }
 
 template <int PR>
 static hipError_t step_p(int material, const StepArgs& a, hipStream_t st) {
     // halo blocks of 6 rows, loads of 2 rows in flight: the fastest of the
     // shapes measured on the 8192^2 workload (halo blocks of 2 to 6 rows, 2 or 3
-    // rows in flight), in FP32 and FP64
+    // rows in flight), in FP32 and FP64; then the wall pass
     switch (material) {
-    case MAT_SVK: launch_march<PR, MAT_SVK, 6, 2>(a, st); break;
-    case MAT_NH: launch_march<PR, MAT_NH, 6, 2>(a, st); break;
-    default: launch_march<PR, MAT_LIN, 6, 2>(a, st); break;
+    case MAT_SVK: launch_march_and_walls<PR, MAT_SVK>(a, st); break;
+    case MAT_NH: launch_march_and_walls<PR, MAT_NH>(a, st); break;
+    default: launch_march_and_walls<PR, MAT_LIN>(a, st); break;
     }
     return hipGetLastError();
 }
@@ -1222,23 +1581,26 @@ hipError_t launch_read(int prec, int material, const ReadArgs& a, hipStream_t st
 int diag_blocks(const Geometry& g) { return ((g.nx + 63) / 64) * ((g.ny + 3) / 4); }
 
 template <int PR>
-static hipError_t diag_p(int material, const ReadArgs& a, double* out, hipStream_t st) {
+static hipError_t diag_p(int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
+                         hipStream_t st) {
     const int nblk = diag_blocks(a.b.g);
     switch (material) {
     case MAT_SVK: hipLaunchKernelGGL((diag_kernel<PR, MAT_SVK>), dim3(nblk), dim3(256), 0, st, a); break;
     case MAT_NH: hipLaunchKernelGGL((diag_kernel<PR, MAT_NH>), dim3(nblk), dim3(256), 0, st, a); break;
     default: hipLaunchKernelGGL((diag_kernel<PR, MAT_LIN>), dim3(nblk), dim3(256), 0, st, a); break;
     }
-    hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(256), 0, st, a.partial, nblk, out);
+    hipLaunchKernelGGL(diag_reduce_kernel, dim3(1), dim3(256), 0, st, static_cast<const double*>(a.partial), nblk,
+                       out, watch, step);
     return hipGetLastError();
 }
 
-hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, hipStream_t st) {
+hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
+                       hipStream_t st) {
     switch (prec) {
-    case PREC_F64: return diag_p<PREC_F64>(material, a, out, st);
-    case PREC_F32: return diag_p<PREC_F32>(material, a, out, st);
-    case PREC_F16: return diag_p<PREC_F16>(material, a, out, st);
-    default: return diag_p<PREC_BF16>(material, a, out, st);
+    case PREC_F64: return diag_p<PREC_F64>(material, a, out, watch, step, st);
+    case PREC_F32: return diag_p<PREC_F32>(material, a, out, watch, step, st);
+    case PREC_F16: return diag_p<PREC_F16>(material, a, out, watch, step, st);
+    default: return diag_p<PREC_BF16>(material, a, out, watch, step, st);
     }
 }
 

@@ -84,6 +84,7 @@ struct Heap {
 struct Request {
     mclbm_params p;
     mclbm_side_spec side[4];
+    std::vector<double> table[4];  // TABLE programs, copied at submission
     std::vector<double> u0;  // empty: zero
     int64_t nsteps = 0;
     double* u_out = nullptr;
@@ -258,25 +259,29 @@ MCLBM_EXPORT int mclbm_server_submit(mclbm_server* sv, const mclbm_params* p, co
                                      const double* u0, int64_t nsteps, double* u_out, int64_t* id_out) {
     if (!sv || !p || !sides || !u_out || !id_out) return set_error(MCLBM_EINVAL, "NULL argument");
     size_t bytes = 0;
-    if (int rc = mclbm_plan(p, &bytes, nullptr)) return rc;
+    if (int rc = mclbm_plan(p, &bytes, nullptr, nullptr)) return rc;
     if (p->precision != sv->cfg.precision)
         return set_error(MCLBM_EINVAL, "request precision differs from the server's");
     if (p->material != MCLBM_SVK && p->material != MCLBM_NEOHOOKE)
         return set_error(MCLBM_EINVAL, "the server runs St. Venant-Kirchhoff and neo-Hooke materials");
+    if (p->boundary_order == 2 || p->time_levels == 1)
+        return set_error(MCLBM_EINVAL, "the server runs the fused step: first-order boundary differences and "
+                                       "the current time level only");
     if (nsteps < 1) return set_error(MCLBM_EINVAL, "nsteps must be >= 1");
     bytes = align_up(bytes);
     if (bytes > sv->pool_bytes - sv->reserved_bytes)
         return set_error(MCLBM_ETOOSMALL, "the request's arena exceeds the server's pool");
-    for (int i = 0; i < 4; i++) {
-        // validate the side programs now rather than at admission
-        const mclbm_side_spec& s = sides[i];
-        if (s.bc < MCLBM_DIRICHLET || s.bc > MCLBM_PERIODIC || s.kind < MCLBM_LOAD_ZERO || s.kind > MCLBM_LOAD_RICKER)
-            return set_error(MCLBM_EINVAL, "unknown side enum");
-    }
+    for (int i = 0; i < 4; i++)  // validate the side programs now rather than at admission
+        if (int rc = check_side_program(&sides[i])) return rc;
     const int64_t id = sv->next_id++;
     Request& r = sv->reqs[id];
     r.p = *p;
     std::memcpy(r.side, sides, sizeof r.side);
+    for (int i = 0; i < 4; i++)
+        if (sides[i].kind == MCLBM_LOAD_TABLE) {
+            r.table[i].assign(sides[i].table, sides[i].table + sides[i].table_len);
+            r.side[i].table = r.table[i].data();
+        }
     if (u0) r.u0.assign(u0, u0 + 2 * (size_t)p->nx * p->ny);
     r.nsteps = nsteps;
     r.u_out = u_out;

@@ -34,7 +34,7 @@ PRECISION = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 SIDE = {"left": 0, "right": 1, "bottom": 2, "top": 3}
 BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}
 LOAD = {"zero": 0, "const": 1, "disp_ramp": 2, "linear_ramp": 3, "sin2_ramp": 4,
-        "sin_pulse": 5, "gauss": 6, "ricker": 7}
+        "sin_pulse": 5, "gauss": 6, "ricker": 7, "table": 8}
 FIELD = {"u": 0, "j": 1, "r": 2, "pi": 3, "h": 4, "p": 5, "s": 6}
 
 
@@ -43,12 +43,15 @@ class mclbm_params(C.Structure):
                 ("precision", C.c_int32), ("dx", C.c_double), ("rho0", C.c_double),
                 ("mu", C.c_double), ("nu", C.c_double), ("tau", C.c_double),
                 ("body", C.c_double * 2), ("tau_plus", C.c_double),
-                ("growth_limit", C.c_double)]
+                ("growth_limit", C.c_double), ("extrap", C.c_int32), ("corner", C.c_int32),
+                ("boundary_order", C.c_int32), ("time_levels", C.c_int32), ("diag_every", C.c_int32),
+                ("reserved_", C.c_int32)]
 
 
 class mclbm_side_spec(C.Structure):
     _fields_ = [("bc", C.c_int32), ("kind", C.c_int32), ("amp", C.c_double * 2),
-                ("t0", C.c_double), ("t1", C.c_double), ("width", C.c_double)]
+                ("t0", C.c_double), ("t1", C.c_double), ("width", C.c_double),
+                ("table", C.POINTER(C.c_double)), ("table_len", C.c_int64)]
 
 
 class mclbm_server_config(C.Structure):
@@ -58,12 +61,12 @@ class mclbm_server_config(C.Structure):
 class mclbm_diag_out(C.Structure):
     _fields_ = [("step", C.c_int64), ("momentum", C.c_double * 2), ("ekin", C.c_double),
                 ("max_u", C.c_double), ("nonfinite", C.c_int32), ("growth", C.c_int32),
-                ("cfl_excess", C.c_int32)]
+                ("cfl_excess", C.c_int32), ("pad_", C.c_int32), ("first_bad_step", C.c_int64)]
 
 
 _vp, _i, _i64, _sz = C.c_void_p, C.c_int, C.c_int64, C.c_size_t
 _sig = {
-    "mclbm_plan": (_i, [C.POINTER(mclbm_params), C.POINTER(_sz), C.POINTER(C.c_double)]),
+    "mclbm_plan": (_i, [C.POINTER(mclbm_params), C.POINTER(_sz), C.POINTER(_sz), C.POINTER(C.c_double)]),
     "mclbm_create": (_i, [C.POINTER(mclbm_params), _vp, _sz, _vp, C.POINTER(_vp)]),
     "mclbm_set_side": (_i, [_vp, _i, C.POINTER(mclbm_side_spec)]),
     "mclbm_init": (_i, [_vp, _vp, _vp, _i]),
@@ -76,8 +79,8 @@ _sig = {
     "mclbm_read": (_i, [_vp, _i, _vp, _i]),
     "mclbm_diag": (_i, [_vp, C.POINTER(mclbm_diag_out)]),
     "mclbm_state_bytes": (_sz, [_vp]),
-    "mclbm_save": (_i, [_vp, _vp, _i]),
-    "mclbm_load": (_i, [_vp, _vp, _i]),
+    "mclbm_save": (_i, [_vp, _vp, _sz, _i]),
+    "mclbm_load": (_i, [_vp, _vp, _sz, _i]),
     "mclbm_destroy": (_i, [_vp]),
     "mclbm_last_error": (C.c_char_p, []),
     "mclbm_server_plan": (_i, [C.POINTER(mclbm_server_config), C.POINTER(_sz)]),
@@ -114,10 +117,17 @@ def mclbm_last_error() -> str:
 
 
 def mclbm_plan(p: mclbm_params):
-    """(arena_bytes, dt) for these parameters."""
-    nbytes, dt = _sz(0), C.c_double(0)
-    _check(_lib.mclbm_plan(C.byref(p), C.byref(nbytes), C.byref(dt)), "mclbm_plan")
+    """(arena_bytes, dt) for these parameters (the alignment: mclbm_plan_align)."""
+    nbytes, align, dt = _sz(0), _sz(0), C.c_double(0)
+    _check(_lib.mclbm_plan(C.byref(p), C.byref(nbytes), C.byref(align), C.byref(dt)), "mclbm_plan")
     return nbytes.value, dt.value
+
+
+def mclbm_plan_align(p: mclbm_params) -> int:
+    """The arena alignment mclbm_plan reports."""
+    align = _sz(0)
+    _check(_lib.mclbm_plan(C.byref(p), None, C.byref(align), None), "mclbm_plan")
+    return align.value
 
 
 def mclbm_create(p: mclbm_params, arena_ptr: int, arena_bytes: int, stream_ptr: int) -> int:
@@ -185,12 +195,12 @@ def mclbm_state_bytes(h: int) -> int:
     return _lib.mclbm_state_bytes(_vp(h))
 
 
-def mclbm_save(h: int, dst_ptr: int, on_device: int) -> None:
-    _check(_lib.mclbm_save(_vp(h), _vp(dst_ptr), on_device), "mclbm_save")
+def mclbm_save(h: int, dst_ptr: int, nbytes: int, on_device: int) -> None:
+    _check(_lib.mclbm_save(_vp(h), _vp(dst_ptr), int(nbytes), on_device), "mclbm_save")
 
 
-def mclbm_load(h: int, src_ptr: int, on_device: int) -> None:
-    _check(_lib.mclbm_load(_vp(h), _vp(src_ptr), on_device), "mclbm_load")
+def mclbm_load(h: int, src_ptr: int, nbytes: int, on_device: int) -> None:
+    _check(_lib.mclbm_load(_vp(h), _vp(src_ptr), int(nbytes), on_device), "mclbm_load")
 
 
 def mclbm_destroy(h: int) -> None:
@@ -251,7 +261,8 @@ def mclbm_server_destroy(h: int) -> None:
 # ---- convenience wrapper (torch owns the device memory and the stream) -------------------------
 
 def make_params(nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0, dx=1.0,
-                body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0) -> mclbm_params:
+                body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0, extrap=0, corner=0, boundary_order=1,
+                time_levels=0, diag_every=0) -> mclbm_params:
     p = mclbm_params()
     p.nx, p.ny = int(nx), int(ny)
     p.material, p.precision = MATERIAL[material], PRECISION[precision]
@@ -259,14 +270,26 @@ def make_params(nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.
     p.body[0], p.body[1] = float(body[0]), float(body[1])
     p.tau_plus = float(tau_plus or 0.0)
     p.growth_limit = float(growth_limit or 0.0)
+    p.extrap = {"copy": 0, "linear": 1}.get(extrap, extrap)
+    p.corner, p.boundary_order, p.diag_every = int(corner), int(boundary_order), int(diag_every)
+    p.time_levels = {"text": 0, "listing": 1}.get(time_levels, time_levels)
+    p.reserved_ = 0
     return p
 
 
-def make_side(bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0) -> mclbm_side_spec:
+def make_side(bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0, table=None) -> mclbm_side_spec:
+    """A side spec; for kind "table", `table` is the program per step (the
+    library copies it, but the array must live until the call that takes the
+    spec returns: the spec keeps a reference in ``_keep``)."""
     s = mclbm_side_spec()
     s.bc, s.kind = BC[bc], LOAD[kind]
     s.amp[0], s.amp[1] = float(amp[0]), float(amp[1])
     s.t0, s.t1, s.width = float(t0), float(t1), float(width)
+    if table is not None:
+        t = np.ascontiguousarray(table, dtype=np.float64).reshape(-1)
+        s.table = t.ctypes.data_as(C.POINTER(C.c_double))
+        s.table_len = t.size
+        s._keep = t
     return s
 
 
@@ -275,13 +298,16 @@ class Sim:
     [comp, ny, nx] on the device (or numpy arrays with ``host=True``)."""
 
     def __init__(self, nx, ny, *, mu, nu, tau, material="svk", precision="f64", rho0=1.0,
-                 dx=1.0, body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0, device="cuda", stream=None):
+                 dx=1.0, body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0, extrap=0, corner=0,
+                 boundary_order=1, time_levels=0, diag_every=0, device="cuda", stream=None):
         import torch
         self.torch = torch
         self.nx, self.ny = int(nx), int(ny)
         self.params = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material,
                                   precision=precision, rho0=rho0, dx=dx, body=body, tau_plus=tau_plus,
-                                  growth_limit=growth_limit)
+                                  growth_limit=growth_limit, extrap=extrap, corner=corner,
+                                  boundary_order=boundary_order, time_levels=time_levels,
+                                  diag_every=diag_every)
         self.arena_bytes, self.dt = mclbm_plan(self.params)
         self.device = torch.device(device)
         self.arena = torch.empty(self.arena_bytes, dtype=torch.uint8, device=self.device)
@@ -306,8 +332,8 @@ class Sim:
     def n(self) -> int:
         return mclbm_stepno(self._h)
 
-    def set_side(self, side, bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0):
-        mclbm_set_side(self._h, SIDE[side], make_side(bc, kind, amp, t0, t1, width))
+    def set_side(self, side, bc, kind="zero", amp=(0.0, 0.0), t0=0.0, t1=0.0, width=0.0, table=None):
+        mclbm_set_side(self._h, SIDE[side], make_side(bc, kind, amp, t0, t1, width, table))
 
     def init(self, u0=None, j0=None):
         t = self.torch
@@ -347,15 +373,28 @@ class Sim:
         d = mclbm_diag(self._h)
         return {"step": d.step, "momentum": np.array([d.momentum[0], d.momentum[1]]),
                 "ekin": d.ekin, "max_u": d.max_u, "nonfinite": bool(d.nonfinite),
-                "growth": bool(d.growth), "cfl_excess": bool(d.cfl_excess)}
+                "growth": bool(d.growth), "cfl_excess": bool(d.cfl_excess),
+                "first_bad_step": int(d.first_bad_step)}
 
-    def save(self):
-        buf = self.torch.empty(mclbm_state_bytes(self._h), dtype=self.torch.uint8, device=self.device)
-        mclbm_save(self._h, buf.data_ptr(), 1)
+    def save(self, host: bool = False):
+        """A checkpoint (header and state) in a device tensor, or with host=True
+        in a numpy byte array."""
+        n = mclbm_state_bytes(self._h)
+        if host:
+            buf = np.empty(n, dtype=np.uint8)
+            mclbm_save(self._h, buf.ctypes.data, n, 0)
+            return buf
+        buf = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        mclbm_save(self._h, buf.data_ptr(), n, 1)
         return buf
 
     def load(self, buf):
-        mclbm_load(self._h, buf.data_ptr(), 1)
+        """Continue from a checkpoint of save() (device tensor or numpy array)."""
+        if isinstance(buf, np.ndarray):
+            b = np.ascontiguousarray(buf, dtype=np.uint8)
+            mclbm_load(self._h, b.ctypes.data, b.nbytes, 0)
+        else:
+            mclbm_load(self._h, buf.data_ptr(), buf.numel() * buf.element_size(), 1)
 
 
 def sim_from_workload(w, precision="f64", **kw) -> Sim:
@@ -398,10 +437,11 @@ class Server:
                 pass
 
     def submit(self, nx, ny, *, mu, nu, tau, material, sides, nsteps, u0=None, rho0=1.0, dx=1.0,
-               body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0) -> int:
-        """sides: {"left": (bc, kind, amp, t0, t1, width) or bc, ...}; missing sides are free."""
+               body=(0.0, 0.0), tau_plus=0.0, growth_limit=0.0, extrap=0, corner=0) -> int:
+        """sides: {"left": (bc, kind, amp, t0, t1, width[, table]) or bc, ...}; missing sides are free."""
         p = make_params(nx, ny, mu=mu, nu=nu, tau=tau, material=material, precision=self.precision,
-                        rho0=rho0, dx=dx, body=body, tau_plus=tau_plus, growth_limit=growth_limit)
+                        rho0=rho0, dx=dx, body=body, tau_plus=tau_plus, growth_limit=growth_limit,
+                        extrap=extrap, corner=corner)
         specs = []
         for name in ("left", "right", "bottom", "top"):
             spec = sides.get(name, "neumann")

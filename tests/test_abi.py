@@ -209,3 +209,96 @@ def test_binding_fails_loudly_without_the_library(tmp_path):
             "    print('raised:', e); sys.exit(0)\nsys.exit(1)")
     p = subprocess.run([sys.executable, "-c", code, str(tmp_path)], capture_output=True, text=True, timeout=300)
     assert p.returncode == 0 and "no fallback" in p.stdout, (p.stdout, p.stderr[-1000:])
+
+
+def test_plan_reports_alignment_and_validates_options(M):
+    p = M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55)
+    assert M.mclbm_plan_align(p) == 256
+    base, _ = M.mclbm_plan(p)
+    for field, value in (("extrap", 2), ("extrap", -1), ("corner", 3), ("corner", -1), ("boundary_order", 3),
+                         ("boundary_order", -1), ("time_levels", 2), ("diag_every", -1), ("reserved_", 1)):
+        q = M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55)
+        setattr(q, field, value)
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_plan(q)
+        assert e.value.code == M.MCLBM_EINVAL, (field, value)
+    # the options of the fused step keep the arena; the multi-pass step holds
+    # T and sigma in FP64 (48 B per node), the printed order two levels of them
+    for kw in (dict(extrap=1), dict(corner=2), dict(diag_every=10)):
+        assert M.mclbm_plan(M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55, **kw))[0] == base
+    plane = 30 * 64
+    b2, _ = M.mclbm_plan(M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55, boundary_order=2))
+    bl, _ = M.mclbm_plan(M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55, time_levels=1))
+    assert b2 >= base + 48 * plane and bl >= base + 96 * plane
+    # zero means first order, for a zero-initialised struct
+    q = M.make_params(40, 30, mu=0.05, nu=0.3, tau=0.55)
+    q.boundary_order = 0
+    assert M.mclbm_plan(q)[0] == base
+
+
+def test_table_program_validation_without_gpu(M):
+    p = M.make_params(16, 16, mu=0.05, nu=0.3, tau=1.0)
+    nbytes, _ = M.mclbm_plan(p)
+    h = M.mclbm_create(p, 1 << 20, nbytes, 0)
+    try:
+        spec = M.make_side("neumann", "table", (1e-3, 0.0))  # no table
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 1, spec)
+        assert e.value.code == M.MCLBM_EINVAL
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_set_side(h, 1, M.make_side("neumann", "table", (1e-3, 0.0), table=[0.0, float("nan")]))
+        assert e.value.code == M.MCLBM_EINVAL
+        spec = M.make_side("neumann", "table", (1e-3, 0.0), table=[0.0, 0.5, 1.0])
+        M.mclbm_set_side(h, 1, spec)
+    finally:
+        M.mclbm_destroy(h)
+
+
+def _header(nx, ny, precision, material, time_levels, step, f_bytes, u_bytes, extra, magic=b"MCLBMCK1", version=1):
+    import struct
+    return struct.pack("<8s6iq3Q", magic, version, nx, ny, precision, material, time_levels, step,
+                       f_bytes, u_bytes, extra)
+
+
+def test_checkpoint_header_is_checked_without_gpu(M):
+    """mclbm_load rejects a short buffer, a foreign file and a checkpoint of
+    another lattice, storage or time order with EINVAL, before any copy."""
+    import numpy as np
+    p = M.make_params(16, 16, mu=0.05, nu=0.3, tau=1.0, precision="f32")
+    nbytes, _ = M.mclbm_plan(p)
+    h = M.mclbm_create(p, 1 << 20, nbytes, 0)
+    try:
+        need = M.mclbm_state_bytes(h)
+        plane = 16 * 64
+        f_bytes, u_bytes = 36 * plane, 16 * plane
+        assert need == 64 + f_bytes + u_bytes
+        cases = [
+            _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0)[:40],                  # short
+            _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0, magic=b"NOTMCLBM"),    # foreign
+            _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0, version=2),            # format version
+            _header(17, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0),                       # lattice
+            _header(16, 16, 0, 0, 0, 5, 72 * plane, u_bytes, 0),                    # storage
+            _header(16, 16, 1, 1, 0, 5, f_bytes, u_bytes, 0),                       # material
+            _header(16, 16, 1, 0, 1, 5, f_bytes, u_bytes, 48 * plane),              # time order
+            _header(16, 16, 1, 0, 0, -3, f_bytes, u_bytes, 0),                      # step
+        ]
+        for k, hd in enumerate(cases):
+            buf = np.zeros(max(len(hd), 64 if k else len(hd)) + (need if k else 0), dtype=np.uint8)
+            buf[:len(hd)] = np.frombuffer(hd, dtype=np.uint8)
+            n = len(hd) if k == 0 else buf.size
+            with pytest.raises(M.MclbmError) as e:
+                M.mclbm_load(h, buf.ctypes.data, n, 0)
+            assert e.value.code == M.MCLBM_EINVAL, k
+        # a matching header over a buffer shorter than the state
+        hd = _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0)
+        buf = np.zeros(need, dtype=np.uint8)
+        buf[:64] = np.frombuffer(hd, dtype=np.uint8)
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_load(h, buf.ctypes.data, need - 1, 0)
+        assert e.value.code == M.MCLBM_EINVAL
+        # saving needs an initialised simulation and room for the state
+        with pytest.raises(M.MclbmError) as e:
+            M.mclbm_save(h, buf.ctypes.data, need, 0)
+        assert e.value.code == M.MCLBM_ESTATE
+    finally:
+        M.mclbm_destroy(h)

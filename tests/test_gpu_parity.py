@@ -55,6 +55,29 @@ def compare(o, s, fields=("u", "p", "j", "r", "pi", "s")):
     return {f: rel(s.read(f), o.read(f)) for f in fields}
 
 
+def node_err(a, b):
+    """Largest node error over all nodes, over the wall rows and columns, and
+    over the four corners, each as a fraction of max |b| (a defect confined to
+    the walls is a small part of a large lattice's L2 norm, not of these)."""
+    scale = np.abs(b).max()
+    d = np.abs(a - b).max(axis=0) / (scale if scale > 0 else 1.0)
+    edge = np.zeros(d.shape, bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    return float(d.max()), float(d[edge].max()), float(d[[0, 0, -1, -1], [0, -1, 0, -1]].max())
+
+
+def compare_nodes(o, s, fields, tol, tag=""):
+    """relative L2 and node-wise errors of fields against the oracle, all within tol"""
+    out = {}
+    for f in fields:
+        a, b = s.read(f), o.read(f)
+        out[f] = (rel(a, b),) + node_err(a, b)
+    print(tag, {f: " ".join(f"{v:.1e}" for v in e) for f, e in out.items()}, flush=True)
+    for f, e in out.items():
+        assert max(e) <= tol, (tag, f, e)
+    return out
+
+
 def print_case(tag):
     print(f"\n[case] {tag}", flush=True)
 
@@ -96,17 +119,11 @@ def test_random_state_parity(M, nx, ny, code, material, precision):
     u0 = W.smooth_field(nx, ny, 0.05, seed=nx + ny)
     j0 = W.random_field(nx, ny, 1e-3, seed=nx * ny)
     o, s = pair(M, nx, ny, walls(code), material=material, nu=0.2, precision=precision, u0=u0, j0=j0)
-    e0 = compare(o, s)
     for n in (1, 9, 30):
         o.step(n - o.n)
         s.step(n - s.n)
-        e = compare(o, s)
-        print(n, {k: f"{v:.2e}" for k, v in e.items()}, flush=True)
-        if precision == "f64":
-            for f, v in e.items():
-                assert v <= TOL["f64"], (n, f, v, e0)
-        else:
-            assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"], (n, e)
+        fields = ("u", "p", "j", "r", "pi", "s") if precision == "f64" else ("u", "p")
+        compare_nodes(o, s, fields, TOL[precision], f"step {n}")
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -143,9 +160,7 @@ def test_small_lattices(M, nx, ny, code):
     o, s = pair(M, nx, ny, walls(code), material="neohooke", nu=0.2, u0=u0)
     o.step(12)
     s.step(12)
-    e = compare(o, s)
-    for f, v in e.items():
-        assert v <= TOL["f64"], (f, v)
+    compare_nodes(o, s, ("u", "p", "j", "r", "pi", "s"), TOL["f64"])
 
 
 def test_body_force_and_units(M):
@@ -269,9 +284,7 @@ def test_tension8192_full_size(M, precision):
     for k in (1, 3):
         o.step(k - o.n)
         s.step(k - s.n)
-        e = compare(o, s, ("u", "p"))
-        print(k, {f: f"{v:.2e}" for f, v in e.items()}, flush=True)
-        assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (k, e)
+        compare_nodes(o, s, ("u", "p"), TOL[precision], f"step {k}")
     del o, s
 
 
@@ -292,9 +305,7 @@ def test_neohooke_full_size(M, precision):
     del u0, j0
     o.step(2)
     s.step(2)
-    e = compare(o, s, ("u", "p"))
-    print({f: f"{v:.2e}" for f, v in e.items()}, flush=True)
-    assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], e
+    compare_nodes(o, s, ("u", "p"), TOL[precision], "step 2")
     del o, s
 
 
@@ -315,9 +326,7 @@ def test_ragged_large_lattice(M, precision):
     del u0, j0
     o.step(2)
     s.step(2)
-    e = compare(o, s, ("u", "p"))
-    print({f: f"{v:.2e}" for f, v in e.items()}, flush=True)
-    assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], e
+    compare_nodes(o, s, ("u", "p"), TOL[precision], "step 2")
     del o, s
 
 
