@@ -245,11 +245,14 @@ int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, int on_device);
 /* Advance nsteps >= 0 time steps, enqueued asynchronously on the stream. */
 int mclbm_step(mclbm_sim* s, int64_t nsteps);
 
-/* Advance nsteps (1..100000) time steps as mclbm_step does, with a HIP event
- * recorded on the stream before each step's launch and after the last, and
- * return the mean duration of one launch in milliseconds.  Synchronises the
+/* Advance nsteps (1..100000) time steps as mclbm_step does, with HIP events
+ * recorded on the stream before each step's launches, after its main kernel
+ * and after the last step, and return the mean duration of one step (ms_step)
+ * and of its main kernel (ms_main: march_kernel of the fused step, without the
+ * wall pass that follows it; the whole step for the multi-pass step), in
+ * milliseconds; either pointer may be NULL, not both.  Synchronises the
  * stream.  For measurement; the results equal those of mclbm_step bitwise. */
-int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step);
+int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_step, double* ms_main);
 
 /* Advance nsteps as mclbm_step does, in runs of `every` (>= 1) steps, and after
  * each run scan the displacement for values that are not finite or, with a

@@ -428,11 +428,16 @@ ReadArgs read_args(const mclbm_sim* s) {
     return a;
 }
 
-// one step on the stream: the fused launch, or the three passes of the
-// multi-pass step
-hipError_t launch_one_step(mclbm_sim* s) {
+// one step on the stream: march_kernel and the wall pass (the event, when set,
+// is recorded between them), or the three passes of the multi-pass step
+hipError_t launch_one_step(mclbm_sim* s, hipEvent_t between = nullptr) {
     const StepArgs a = step_args(s);
-    if (!s->L.multipass) return launch_step(s->p.precision, s->p.material, a, s->stream);
+    if (!s->L.multipass) {
+        hipError_t e = launch_step(s->p.precision, s->p.material, a, s->stream);
+        if (e == hipSuccess && between) e = hipEventRecord(between, s->stream);
+        if (e == hipSuccess) e = launch_walls(s->p.precision, s->p.material, a, s->stream);
+        return e;
+    }
     PassArgs pa;
     pa.s = a;
     // level n goes to the buffers not holding level n - 1
@@ -445,6 +450,7 @@ hipError_t launch_one_step(mclbm_sim* s) {
     hipError_t e = launch_stress_pass(s->p.material, b, pa.T, s->stream);
     if (e == hipSuccess) e = launch_source_pass(b, pa.T, pa.sig, s->stream);
     if (e == hipSuccess) e = launch_pass_step(s->p.precision, pa, s->stream);
+    if (e == hipSuccess && between) e = hipEventRecord(between, s->stream);
     return e;
 }
 
@@ -505,44 +511,47 @@ MCLBM_EXPORT int mclbm_step_checked(mclbm_sim* s, int64_t nsteps, int64_t every,
     return MCLBM_OK;
 }
 
-MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_per_step) {
+MCLBM_EXPORT int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_step, double* ms_main) {
     if (int e = check_steppable(s, nsteps)) return e;
     if (nsteps < 1 || nsteps > 100000) return fail(MCLBM_EINVAL, "nsteps must be in 1..100000");
-    if (!ms_per_step) return fail(MCLBM_EINVAL, "output pointer must not be NULL");
-    // event i is recorded before the launch of step i, event nsteps after the last
-    std::vector<hipEvent_t> ev((size_t)(nsteps + 1), nullptr);
+    if (!ms_step && !ms_main) return fail(MCLBM_EINVAL, "both output pointers are NULL");
+    // a[i] before step i's launches, b[i] after its main kernel, a[nsteps] after the last step
+    std::vector<hipEvent_t> a((size_t)(nsteps + 1), nullptr), b((size_t)nsteps, nullptr);
     int rc = MCLBM_OK;
-    for (auto& e : ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
-            e = nullptr;
-            rc = fail(MCLBM_EHIP, "hipEventCreate failed");
-            break;
-        }
-    }
+    for (auto* v : {&a, &b})
+        for (auto& e : *v)
+            if (rc == MCLBM_OK && hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+                rc = fail(MCLBM_EHIP, "hipEventCreate failed");
+            }
     for (int64_t i = 0; rc == MCLBM_OK && i < nsteps; i++) {
-        hipError_t e = hipEventRecord(ev[i], s->stream);
-        if (e == hipSuccess) e = launch_one_step(s);
+        hipError_t e = hipEventRecord(a[i], s->stream);
+        if (e == hipSuccess) e = launch_one_step(s, b[i]);
         if (e != hipSuccess) {
             rc = fail(MCLBM_EHIP, "step launch failed: %s", hipGetErrorString(e));
             break;
         }
         advance_one(s);
     }
-    if (rc == MCLBM_OK && hipEventRecord(ev[nsteps], s->stream) != hipSuccess)
+    if (rc == MCLBM_OK && hipEventRecord(a[nsteps], s->stream) != hipSuccess)
         rc = fail(MCLBM_EHIP, "hipEventRecord failed");
     if (rc == MCLBM_OK && hipStreamSynchronize(s->stream) != hipSuccess)
         rc = fail(MCLBM_EHIP, "hipStreamSynchronize failed");
-    double total = 0;
+    double tstep = 0, tmain = 0;
     for (int64_t k = 0; rc == MCLBM_OK && k < nsteps; k++) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess)
+        float m1 = 0, m2 = 0;
+        if (hipEventElapsedTime(&m1, a[k], a[k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&m2, a[k], b[k]) != hipSuccess)
             rc = fail(MCLBM_EHIP, "hipEventElapsedTime failed");
-        total += ms;
+        tstep += m1;
+        tmain += m2;
     }
-    for (auto e : ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto* v : {&a, &b})
+        for (auto e : *v)
+            if (e) (void)hipEventDestroy(e);
     if (rc != MCLBM_OK) return rc;
-    *ms_per_step = total / nsteps;
+    if (ms_step) *ms_step = tstep / nsteps;
+    if (ms_main) *ms_main = tmain / nsteps;
     return MCLBM_OK;
 }
 

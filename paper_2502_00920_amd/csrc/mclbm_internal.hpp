@@ -116,9 +116,11 @@ int set_error(int code, const char* msg);
 // validation of a side program (the checks of mclbm_set_side)
 int check_side_program(const void* spec);
 
-// prec: PREC_F64 / F32 / F16 / BF16.  One launch: march_kernel over every node,
-// walls included.
+// prec: PREC_F64 / F32 / F16 / BF16.  The fused step: march_kernel over every
+// node (launch_step), then the wall pass that redoes the nodes on non-periodic
+// sides with the wall rules (launch_walls; nothing for a periodic lattice).
 hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st);
+hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st);
 // the multi-pass step: stresses, source, step (three launches)
 hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st);
 hipError_t launch_source_pass(const InitLike& b, const double* T, double* sig, hipStream_t st);

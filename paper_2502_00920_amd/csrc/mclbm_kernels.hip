@@ -1494,21 +1494,39 @@ hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipS
 }
 
 template <int PR, int MAT>
-static void launch_march_and_walls(const StepArgs& a, hipStream_t st) {
-    launch_march<PR, MAT, 6, 2>(a, st);
+static void launch_walls_pm(const StepArgs& a, hipStream_t st) {
     const int nseg = wall_segs(a.g).total;
     if (nseg > 0) hipLaunchKernelGGL((wall_kernel<PR, MAT>), dim3(nseg), dim3(256), 0, st, a);
+}
+
+template <int PR>
+static hipError_t walls_p(int material, const StepArgs& a, hipStream_t st) {
+    switch (material) {
+    case MAT_SVK: launch_walls_pm<PR, MAT_SVK>(a, st); break;
+    case MAT_NH: launch_walls_pm<PR, MAT_NH>(a, st); break;
+    default: launch_walls_pm<PR, MAT_LIN>(a, st); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: return walls_p<PREC_F64>(material, a, st);
+    case PREC_F32: return walls_p<PREC_F32>(material, a, st);
+    case PREC_F16: return walls_p<PREC_F16>(material, a, st);
+    default: return walls_p<PREC_BF16>(material, a, st);
+    }
 }
 
 template <int PR>
 static hipError_t step_p(int material, const StepArgs& a, hipStream_t st) {
     // halo blocks of 6 rows, loads of 2 rows in flight: the fastest of the
     // shapes measured on the 8192^2 workload (halo blocks of 2 to 6 rows, 2 or 3
-    // rows in flight), in FP32 and FP64; then the wall pass
+    // rows in flight), in FP32 and FP64
     switch (material) {
-    case MAT_SVK: launch_march_and_walls<PR, MAT_SVK>(a, st); break;
-    case MAT_NH: launch_march_and_walls<PR, MAT_NH>(a, st); break;
-    default: launch_march_and_walls<PR, MAT_LIN>(a, st); break;
+    case MAT_SVK: launch_march<PR, MAT_SVK, 6, 2>(a, st); break;
+    case MAT_NH: launch_march<PR, MAT_NH, 6, 2>(a, st); break;
+    default: launch_march<PR, MAT_LIN, 6, 2>(a, st); break;
     }
     return hipGetLastError();
 }

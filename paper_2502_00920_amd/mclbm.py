@@ -71,7 +71,7 @@ _sig = {
     "mclbm_set_side": (_i, [_vp, _i, C.POINTER(mclbm_side_spec)]),
     "mclbm_init": (_i, [_vp, _vp, _vp, _i]),
     "mclbm_step": (_i, [_vp, _i64]),
-    "mclbm_step_timed": (_i, [_vp, _i64, C.POINTER(C.c_double)]),
+    "mclbm_step_timed": (_i, [_vp, _i64, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "mclbm_step_checked": (_i, [_vp, _i64, _i64, C.POINTER(_i64)]),
     "mclbm_copy": (_i, [_vp, _vp, _sz, _vp]),
     "mclbm_stepno": (_i64, [_vp]),
@@ -160,11 +160,12 @@ def mclbm_step_checked(h: int, nsteps: int, every: int):
     return True, done.value
 
 
-def mclbm_step_timed(h: int, nsteps: int) -> float:
-    """Mean ms of one step launch over nsteps steps, from HIP events around each."""
-    ms = C.c_double(0)
-    _check(_lib.mclbm_step_timed(_vp(h), int(nsteps), C.byref(ms)), "mclbm_step_timed")
-    return ms.value
+def mclbm_step_timed(h: int, nsteps: int):
+    """(mean ms of one step, mean ms of its main kernel) over nsteps steps, from
+    HIP events around each step's launches and after its main kernel."""
+    ms, mm = C.c_double(0), C.c_double(0)
+    _check(_lib.mclbm_step_timed(_vp(h), int(nsteps), C.byref(ms), C.byref(mm)), "mclbm_step_timed")
+    return ms.value, mm.value
 
 
 def mclbm_copy(dst_ptr: int, src_ptr: int, nbytes: int, stream_ptr: int) -> None:
@@ -359,8 +360,9 @@ class Sim:
         or a |u| above the growth limit."""
         return mclbm_step_checked(self._h, n, every)
 
-    def step_timed(self, n: int) -> float:
-        """Advance n steps; returns the mean ms of one step launch."""
+    def step_timed(self, n: int):
+        """Advance n steps; returns (mean ms of one step, mean ms of its main
+        kernel, march_kernel of the fused step)."""
         return mclbm_step_timed(self._h, n)
 
     def read(self, field: str, host: bool = True):

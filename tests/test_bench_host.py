@@ -47,10 +47,20 @@ def test_counter_calibration(tmp_path):
     f32 = out["f32"]
     assert f32["read_bytes"] == pytest.approx(2 * 2000.0 * 1024)
     assert f32["written_bytes"] == pytest.approx(1500.0 * 1024)
-    assert f32["algorithmic_bytes"] == 104 * 64 * 64
-    assert f32["ratio"] == pytest.approx((4000.0 + 1500.0) * 1024 / (104 * 64 * 64))
+    # the method's state per update (populations, u and j read and written),
+    # and what the kernel must move without a stored j
+    assert f32["algorithmic_bytes"] == 120 * 64 * 64 and f32["compulsory_bytes"] == 104 * 64 * 64
+    assert f32["ratio"] == pytest.approx((4000.0 + 1500.0) * 1024 / (120 * 64 * 64))
+    assert f32["ratio_compulsory"] == pytest.approx((4000.0 + 1500.0) * 1024 / (104 * 64 * 64))
     assert "f64" not in out and out["kernel_hash"] == bench.kernel_hash()
     assert json.loads(out_file.read_text())["f32"]["read_bytes"] == f32["read_bytes"]
+
+
+def test_bytes_per_update():
+    """Algorithmic bytes per lattice update by storage: 9 populations, u in FP64
+    and j, each read and written once; the compulsory bytes leave out j."""
+    assert bench.BYTES_PER_LUP == {"f32": 120, "f64": 208, "f16": 84, "bf16": 84}
+    assert bench.COMPULSORY_BYTES_PER_LUP == {"f32": 104, "f64": 176, "f16": 68, "bf16": 68}
 
 
 def test_counter_calibration_needs_the_copy(tmp_path):
