@@ -335,6 +335,65 @@ def error_growth(steps: int = 20000, every: int = 2000) -> dict:
     return {"workload": f"{w.name}, FP64 storage as the reference", "history": hist}
 
 
+def stability(precision: str = "f64", opts=None) -> dict:
+    """The workloads at their full lengths: where each loses stability, and how
+    fast a perturbation grows before that.  Each runs twice on the GPU, from its
+    start and from its start plus seeded noise of 1e-12 dx on u; every `every`
+    steps the largest |u| and the relative L2 distance of the two runs' u are
+    recorded, until the run is no longer finite or its steps are done.  The
+    growth rate is the slope of ln(distance) per step over the checkpoints where
+    the distance lies between 1e-9 and 1e-3 (the perturbation still small).
+    Where the two runs differ most at the last finite checkpoint is recorded
+    (node and distance from the nearest wall).  opts: options of the step
+    (mclbm.Sim keywords: extrap, corner, tau_plus, boundary_order, time_levels)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2502_00920_amd import mclbm
+    from paper_2502_00920_amd import workloads as W
+
+    cases = [(W.tension32(), 50), (W.shear128(0.0), 100), (W.shear128(0.25), 100), (W.shear128(0.45), 5),
+             (W.beam2048(), 500)]
+    opts = dict(opts or {})
+    out = {"precision": precision, "options": opts, "perturbation": "uniform noise of 1e-12 dx on u0, seed 99",
+           "rows": []}
+    for w, every in cases:
+        a, b = mclbm.sim_from_workload(w, precision, **opts), mclbm.sim_from_workload(w, precision, **opts)
+        u0 = w.u0()
+        a.init(u0)
+        b.init(u0 + W.random_field(w.nx, w.ny, 1e-12 * w.dx, 99))
+        hist, diverged, where = [], None, None
+        for n in range(every, w.steps + 1, every):
+            a.step(every)
+            b.step(every)
+            ua, ub = a.read("u"), b.read("u")
+            umax = float(np.abs(ua).max()) if np.isfinite(ua).all() else float("inf")
+            d = float(np.linalg.norm(ua - ub) / max(np.linalg.norm(ua), 1e-300)) if math.isfinite(umax) else float("inf")
+            hist.append((n, umax, d))
+            if not math.isfinite(umax) or umax > 1e3 * w.nx * w.dx:
+                diverged = n
+                break
+            diff = np.abs(ua - ub).max(axis=0)
+            y, x = np.unravel_index(int(np.argmax(diff)), diff.shape)
+            where = {"step": n, "node": [int(x), int(y)],
+                     "from_wall": int(min(x, w.nx - 1 - x, y, w.ny - 1 - y))}
+        pts = [(n, math.log(d)) for n, _, d in hist if 1e-9 < d < 1e-3]
+        rate = None
+        if len(pts) >= 3:
+            xs, ys = np.array([p[0] for p in pts], float), np.array([p[1] for p in pts])
+            rate = float(np.polyfit(xs, ys, 1)[0])
+        row = {"workload": w.name, "nu": w.nu, "tau": w.tau, "steps": w.steps, "diverged_by": diverged,
+               "largest_difference_before": where,
+               "growth_rate_per_step": rate,
+               "growth_factor_per_step": None if rate is None else math.exp(rate),
+               "history": [(n, round(u, 6), float(f"{d:.3e}")) for n, u, d in hist[:: max(1, len(hist) // 40)]]}
+        print("# " + json.dumps({k: v for k, v in row.items() if k != "history"}), file=sys.stderr, flush=True)
+        out["rows"].append(row)
+        del a, b
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +405,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--error-growth", action="store_true",
                     help="print the long-run error of each storage format against FP64 as one JSON line and exit")
+    ap.add_argument("--stability", choices=["f64", "f32"],
+                    help="run the workloads at their full lengths twice (perturbed start) and print where each "
+                         "loses stability and how fast perturbations grow, as one JSON line, and exit")
+    ap.add_argument("--stability-opts", default="{}",
+                    help="with --stability: step options as JSON, e.g. '{\"tau_plus\": 1.0}'")
     ap.add_argument("--configs", action="store_true",
                     help="print the per-configuration rates (GPU and CPU oracle) as one JSON line and exit")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -370,6 +434,9 @@ def main():
         return
     if args.error_growth:
         print(json.dumps(error_growth()), flush=True)
+        return
+    if args.stability:
+        print(json.dumps(stability(args.stability, json.loads(args.stability_opts))), flush=True)
         return
 
     modes = ["f32", "f64", "f16", "bf16"] if args.mode == "all" else [args.mode]

@@ -17,7 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "mclbm_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# MCLBM_ORACLE_LIB: another build of the same source (e.g. with other floating-
+# point contraction flags), for measuring how rounding order alone moves results
+LIB = os.environ.get("MCLBM_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 SIDE = {"left": 0, "right": 1, "bottom": 2, "top": 3}
 BC = {"dirichlet": 0, "neumann": 1, "periodic": 2}

@@ -223,22 +223,32 @@ def test_shear128_poisson_sweep(M, nu, checkpoints, precision):
         assert e["u"] <= TOL[precision] and e["p"] <= TOL[precision], (n, e)
 
 
+def fp_order_drift():
+    """The relative L2 distance of u and P between two FP64 builds of the oracle
+    that differ only in rounding order (fused multiply-adds or not), on the
+    cantilever workload, per step (tests/golden/make_fp_order_drift.py)."""
+    import json
+    with open(os.path.join(os.path.dirname(__file__), "golden", "beam2048_fp_order_drift.json")) as f:
+        return {r["step"]: r for r in json.load(f)["rows"]}
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_beam2048(M, precision):
     """The cantilever pulse (Gaussian traction, 2048 x 128) through its pulse and
     well into the free vibration that follows: 3000 of its 50000 steps (it loses
-    stability near step 21000).  The rounding differences between two FP64
-    implementations that order their operations differently accumulate over the
-    free vibration (a kernel built without fused multiply-adds drifts the same,
-    3.4e-12 at step 3000): P differs
-    by 2.7e-13 at step 1000, 1.75e-12 at 2000, 3.6e-12 at 3000 and 5.7e-12 at
-    4000 (u by 30 times less).  The FP64 bar of 1e-12 is asserted to step 1000;
-    at step 3000 a long-horizon bound of 1e-11 is.  FP32 stays below 2e-6 and
-    keeps its bar of 1e-5 throughout."""
+    stability near step 21000).  Rounding differences are amplified over the
+    free vibration: two FP64 builds of the oracle itself, with and without fused
+    multiply-adds, drift apart by 1.6e-13 (P) at step 1000, 1.8e-12 at 2000 and
+    3.5e-12 at 3000.  The FP64 bar is 1e-12, or twice that drift of the oracle
+    against itself where it is larger.  FP32 keeps its bar of 1e-5 throughout."""
     print_case(f"beam2048x128 {precision}")
+    drift = fp_order_drift()
     for n, e, umax in run_workload(M, W.beam2048(), precision, [50, 150, 1000, 3000]):
-        tol = 1e-11 if precision == "f64" and n > 1000 else TOL[precision]
-        assert e["u"] <= tol and e["p"] <= tol, (n, e)
+        for f in ("u", "p"):
+            tol = TOL[precision]
+            if precision == "f64" and n in drift:
+                tol = max(tol, 2.0 * drift[n][f])
+            assert e[f] <= tol, (n, f, e, tol)
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
