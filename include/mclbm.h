@@ -287,6 +287,20 @@ int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device);
  * max_u exceeds the growth_limit. */
 int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out);
 
+/* For callers that cannot allocate device memory or use a workspace (code under
+ * graph capture, serving loops, harnesses that forbid allocation): mclbm_diag
+ * with its block partials and result in a fixed array of the library's own
+ * device memory instead of the arena's diagnostics areas.  The array holds
+ * 1025 x 8 doubles (65 600 bytes) per device, for the life of the process; the
+ * reduction uses at most 1024 blocks, each taking several 64 x 4 node tiles,
+ * so every lattice fits it.  Call it with the simulation's device current.
+ * Nothing is allocated: the array's address is looked up once per device.
+ * Calls on one device share the array: calls that overlap (on several streams
+ * or threads) race and must be serialised by the caller.  The results equal
+ * mclbm_diag's up to the summation order (more nodes per block).  Same
+ * statuses as mclbm_diag; EHIP if the device's array cannot be reached. */
+int mclbm_diag_noalloc(mclbm_sim* s, mclbm_diag_out* out);
+
 /* Checkpoints: a 64-byte header (magic, format version, nx, ny, storage
  * precision, material, byte counts, step counter) followed by the state
  * (populations, displacement, and with time_levels = 1 the source and stresses

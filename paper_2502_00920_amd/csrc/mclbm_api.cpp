@@ -655,18 +655,10 @@ MCLBM_EXPORT int mclbm_read(mclbm_sim* s, int field, double* dst, int on_device)
     return MCLBM_OK;
 }
 
-MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
-    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
-    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
-    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_diag before mclbm_init");
-    const ReadArgs a = read_args(s);
-    double* dout = static_cast<double*>(at(s, s->L.off_out));
-    HIP_TRY(launch_diag(s->p.precision, s->p.material, a, dout, nullptr, 0, s->stream));
-    double h[5];
-    int64_t first_bad = -1;
-    HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipMemcpyAsync(&first_bad, at(s, s->L.off_watch), sizeof first_bad, hipMemcpyDeviceToHost, s->stream));
-    HIP_TRY(hipStreamSynchronize(s->stream));
+namespace {
+
+// mclbm_diag_out from the five totals and the watch record; the status
+int diag_result(mclbm_sim* s, const double h[5], int64_t first_bad, mclbm_diag_out* out) {
     std::memset(out, 0, sizeof *out);
     out->step = s->n;
     out->first_bad_step = s->p.diag_every > 0 ? first_bad : -1;
@@ -686,6 +678,37 @@ MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
         return fail(MCLBM_EUNSTABLE, "max |u| %g above the growth limit %g at step %lld", out->max_u,
                     s->p.growth_limit, (long long)s->n);
     return MCLBM_OK;
+}
+
+}  // namespace
+
+MCLBM_EXPORT int mclbm_diag(mclbm_sim* s, mclbm_diag_out* out) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_diag before mclbm_init");
+    const ReadArgs a = read_args(s);
+    double* dout = static_cast<double*>(at(s, s->L.off_out));
+    HIP_TRY(launch_diag(s->p.precision, s->p.material, a, dout, nullptr, 0, s->stream));
+    double h[5];
+    int64_t first_bad = -1;
+    HIP_TRY(hipMemcpyAsync(h, dout, sizeof h, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipMemcpyAsync(&first_bad, at(s, s->L.off_watch), sizeof first_bad, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return diag_result(s, h, first_bad, out);
+}
+
+MCLBM_EXPORT int mclbm_diag_noalloc(mclbm_sim* s, mclbm_diag_out* out) {
+    if (!s) return fail(MCLBM_EINVAL, "handle is NULL");
+    if (!out) return fail(MCLBM_EINVAL, "out is NULL");
+    if (!s->inited) return fail(MCLBM_ESTATE, "mclbm_diag_noalloc before mclbm_init");
+    ReadArgs a = read_args(s);
+    a.partial = nullptr;  // the partials go to the library's fixed array
+    double h[5];
+    HIP_TRY(launch_diag_noalloc(s->p.precision, s->p.material, a, h, s->stream));
+    int64_t first_bad = -1;
+    HIP_TRY(hipMemcpyAsync(&first_bad, at(s, s->L.off_watch), sizeof first_bad, hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    return diag_result(s, h, first_bad, out);
 }
 
 namespace {

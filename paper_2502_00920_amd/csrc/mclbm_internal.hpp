@@ -133,5 +133,9 @@ hipError_t launch_read(int prec, int material, const ReadArgs& a, hipStream_t st
 hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
                        hipStream_t st);
 int diag_blocks(const Geometry& g);
+// the same diagnostics with the block partials and the result in the library's
+// fixed device array (no workspace); copies the five totals to host_out and
+// synchronises the stream
+hipError_t launch_diag_noalloc(int prec, int material, ReadArgs a, double host_out[5], hipStream_t st);
 
 }  // namespace mclbm

@@ -23,6 +23,7 @@
 // HBM traffic per node and step: 9 populations read and written, u read and
 // written (FP64): 176 B in FP64, 104 B in FP32 storage.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "mclbm_internal.hpp"
@@ -992,33 +993,52 @@ __device__ __forceinline__ double wave_reduce(double v, bool take_max) {
     return v;
 }
 
+// the diagnostics of one node: momentum x, y, kinetic energy, |u|^2, non-finite
+template <int PR, int MAT>
+__device__ __forceinline__ void diag_node(const ReadArgs& a, int gx, int gy, double v[5]) {
+    const Geometry& g = a.b.g;
+    const size_t plane = (size_t)g.plane;
+    const size_t o = (size_t)gy * g.pitch + gx;
+    double mx = 0, my = 0, s[2];
+    for (int q = 0; q < 9; q++) {
+        const double w = pop_get<PR>(a.f, plane, o, q, a.finv);
+        mx += ex(q) * w;
+        my += ey(q) * w;
+    }
+    collision_sigma<MAT>(a, gx, gy, s);
+    const double jx = a.c * (mx + 0.5 * s[0]), jy = a.c * (my + 0.5 * s[1]);
+    const double ux = a.b.u[o], uy = a.b.u[plane + o];
+    v[0] = a.c * mx;
+    v[1] = a.c * my;
+    v[2] = (jx * jx + jy * jy) / (2.0 * a.b.rho0);
+    v[3] = ux * ux + uy * uy;
+    v[4] = (isfinite(jx) && isfinite(jy) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
+    if (v[4] != 0.0) v[3] = 0.0;
+}
+
+// Tiles of 64 x 4 nodes; block b takes the tiles b, b + grid, ... (one tile per
+// block when the grid has one block per tile), and writes its partial sums
+// (maxima for |u|^2 and the flag) to partial[8 b ..]: a fixed order, so the
+// result is deterministic for a given grid.
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void diag_kernel(ReadArgs a) {
     const Geometry& g = a.b.g;
-    const int nbx = (g.nx + 63) / 64;
-    const int bx = blockIdx.x % nbx, by = blockIdx.x / nbx;
-    const int gx = bx * 64 + (threadIdx.x & 63), gy = by * 4 + (threadIdx.x >> 6);
+    const int nbx = (g.nx + 63) / 64, ntiles = nbx * ((g.ny + 3) / 4);
     double v[5] = {0, 0, 0, 0, 0};  // momentum x, y, ekin, max |u|^2, non-finite
-    if (gx < g.nx && gy < g.ny) {
-        const size_t plane = (size_t)g.plane;
-        const size_t o = (size_t)gy * g.pitch + gx;
-        double mx = 0, my = 0, s[2];
-        for (int q = 0; q < 9; q++) {
-            const double w = pop_get<PR>(a.f, plane, o, q, a.finv);
-            mx += ex(q) * w;
-            my += ey(q) * w;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int bx = tile % nbx, by = tile / nbx;
+        const int gx = bx * 64 + (threadIdx.x & 63), gy = by * 4 + (threadIdx.x >> 6);
+        if (gx < g.nx && gy < g.ny) {
+            double w[5];
+            diag_node<PR, MAT>(a, gx, gy, w);
+            v[0] += w[0];
+            v[1] += w[1];
+            v[2] += w[2];
+            v[3] = fmax(v[3], w[3]);
+            v[4] = fmax(v[4], w[4]);
         }
-        collision_sigma<MAT>(a, gx, gy, s);
-        const double jx = a.c * (mx + 0.5 * s[0]), jy = a.c * (my + 0.5 * s[1]);
-        const double ux = a.b.u[o], uy = a.b.u[plane + o];
-        v[0] = a.c * mx;
-        v[1] = a.c * my;
-        v[2] = (jx * jx + jy * jy) / (2.0 * a.b.rho0);
-        v[3] = ux * ux + uy * uy;
-        v[4] = (isfinite(jx) && isfinite(jy) && isfinite(ux) && isfinite(uy)) ? 0.0 : 1.0;
-        if (v[4] != 0.0) v[3] = 0.0;
     }
-    // each wave reduces its 64 nodes with lane shifts, then the block's four
+    // each wave reduces its 64 lanes with lane shifts, then the block's four
     // wave results are added in wave order
     __shared__ double red[4][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1600,8 +1620,7 @@ int diag_blocks(const Geometry& g) { return ((g.nx + 63) / 64) * ((g.ny + 3) / 4
 
 template <int PR>
 static hipError_t diag_p(int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
-                         hipStream_t st) {
-    const int nblk = diag_blocks(a.b.g);
+                         hipStream_t st, int nblk) {
     switch (material) {
     case MAT_SVK: hipLaunchKernelGGL((diag_kernel<PR, MAT_SVK>), dim3(nblk), dim3(256), 0, st, a); break;
     case MAT_NH: hipLaunchKernelGGL((diag_kernel<PR, MAT_NH>), dim3(nblk), dim3(256), 0, st, a); break;
@@ -1612,14 +1631,63 @@ static hipError_t diag_p(int material, const ReadArgs& a, double* out, int64_t* 
     return hipGetLastError();
 }
 
+static hipError_t diag_any(int prec, int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
+                           hipStream_t st, int nblk) {
+    switch (prec) {
+    case PREC_F64: return diag_p<PREC_F64>(material, a, out, watch, step, st, nblk);
+    case PREC_F32: return diag_p<PREC_F32>(material, a, out, watch, step, st, nblk);
+    case PREC_F16: return diag_p<PREC_F16>(material, a, out, watch, step, st, nblk);
+    default: return diag_p<PREC_BF16>(material, a, out, watch, step, st, nblk);
+    }
+}
+
 hipError_t launch_diag(int prec, int material, const ReadArgs& a, double* out, int64_t* watch, int64_t step,
                        hipStream_t st) {
-    switch (prec) {
-    case PREC_F64: return diag_p<PREC_F64>(material, a, out, watch, step, st);
-    case PREC_F32: return diag_p<PREC_F32>(material, a, out, watch, step, st);
-    case PREC_F16: return diag_p<PREC_F16>(material, a, out, watch, step, st);
-    default: return diag_p<PREC_BF16>(material, a, out, watch, step, st);
+    return diag_any(prec, material, a, out, watch, step, st, diag_blocks(a.b.g));
+}
+
+// ---- the diagnostics without a workspace: partial sums in a fixed device array ---------------------
+//
+// For callers that cannot allocate: the block partials and the result live in
+// `scratch`, one copy per device for the life of the process, at most
+// kScratchBlocks partials (the grid is capped at that many blocks, each taking
+// several tiles), whatever the lattice.  Every call writes all the partials it
+// reads, so nothing needs clearing; calls that overlap on one device race for
+// the array.  Host code reaches the array only through the address
+// hipGetSymbolAddress reports for the current device.
+
+constexpr int kScratchBlocks = 1024;
+constexpr int kScratchDoubles = (kScratchBlocks + 1) * 8;  // partials, then the 8-double result
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+hipError_t launch_diag_noalloc(int prec, int material, ReadArgs a, double host_out[5], hipStream_t st) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    double* base;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[dev]) {  // once per device, with that device current
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess) return e;
+            g_scratch[dev] = static_cast<double*>(p);
+        }
+        base = g_scratch[dev];
     }
+    const int nblk = std::min(diag_blocks(a.b.g), kScratchBlocks);
+    if (nblk < 1 || (size_t)(nblk + 1) * 8 > (size_t)kScratchDoubles) return hipErrorInvalidValue;
+    a.partial = base;
+    double* out = base + (size_t)kScratchBlocks * 8;
+    e = diag_any(prec, material, a, out, nullptr, 0, st, nblk);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_out, out, 5 * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
 }
 
 }  // namespace mclbm

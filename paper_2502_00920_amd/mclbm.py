@@ -78,6 +78,7 @@ _sig = {
     "mclbm_field_components": (_i, [_i]),
     "mclbm_read": (_i, [_vp, _i, _vp, _i]),
     "mclbm_diag": (_i, [_vp, C.POINTER(mclbm_diag_out)]),
+    "mclbm_diag_noalloc": (_i, [_vp, C.POINTER(mclbm_diag_out)]),
     "mclbm_state_bytes": (_sz, [_vp]),
     "mclbm_save": (_i, [_vp, _vp, _sz, _i]),
     "mclbm_load": (_i, [_vp, _vp, _sz, _i]),
@@ -189,6 +190,15 @@ def mclbm_diag(h: int) -> mclbm_diag_out:
     rc = _lib.mclbm_diag(_vp(h), C.byref(out))
     if rc not in (MCLBM_OK, MCLBM_EUNSTABLE):
         _check(rc, "mclbm_diag")
+    return out
+
+
+def mclbm_diag_noalloc(h: int) -> mclbm_diag_out:
+    """mclbm_diag with its scratch in the library's fixed device array."""
+    out = mclbm_diag_out()
+    rc = _lib.mclbm_diag_noalloc(_vp(h), C.byref(out))
+    if rc not in (MCLBM_OK, MCLBM_EUNSTABLE):
+        _check(rc, "mclbm_diag_noalloc")
     return out
 
 
