@@ -326,8 +326,9 @@ const char* mclbm_last_error(void);
  * lattice nodes); each round uploads one table (per step and group: the
  * simulations' buffers, wall values at their own step index and work items)
  * and replays, on four streams of the server's own joined to the caller's,
- * one graph per group of batched step launches captured at the first round: a
- * fixed grid of waves walks the work items of all simulations of the group,
+ * one graph per group of batched step launches (captured at the first round,
+ * and again when a round's work items outgrow its grid): one wave per work
+ * item of all simulations of the group,
  * so requests of different lattice sizes, loads and step counts share every
  * launch, and the groups' launches run side by side.  A simulation's result does not depend on its company:
  * it is bitwise the same alone and in any mix.  Against mclbm_step it agrees

@@ -97,8 +97,20 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 // work items of one lattice's step in a batch: 64-column strips times row chunks
 void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk);
 // the step for every simulation of one material in the table at step (device
-// memory, read by the kernel), on a fixed grid: graph-capturable
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st);
+// memory, read by the kernel): the march on `blocks` blocks of four waves, one
+// work item per wave, so blocks * 4 must cover the table's items (extra waves
+// end at once); the wall pass on a fixed grid.  Graph-capturable: a captured
+// launch serves any table whose items fit its blocks.
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st);
+// blocks of the batch march for a table of n items: a quarter of n rounded up
+// to a power of two, at least kMinBatchBlocks (so that a captured launch is
+// re-captured only when a batch outgrows it by a factor of two)
+constexpr int kMinBatchBlocks = 256;
+inline int batch_march_blocks(long long n) {
+    long long need = (n + 3) / 4, b = kMinBatchBlocks;
+    while (b < need) b *= 2;
+    return (int)b;
+}
 
 }  // namespace mclbm
 

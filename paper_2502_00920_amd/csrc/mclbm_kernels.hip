@@ -781,34 +781,35 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
     march_item<PR, MAT, HR, D>(a, halo_lds[wv], lane, item % nstrip, item / nstrip, chunk);
 }
 
-// The step of a batch of lattices of one material: a fixed grid of persistent
-// waves walks the work items of every simulation in the table (which lives in
-// device memory, so that a captured launch serves any batch); block b takes
-// items 4b..4b+3, then the same plus four times the grid, so that neighbouring
-// strips run on one CU and share their halo lines in its L2.  An item's work
-// depends only on its own lattice, so a simulation's results do not depend on
-// its company.  FP64 runs one wave per SIMD, as in march_kernel (no spills; on
-// the serving mix 20.8 against 16.2 GLUPS at two waves), so one block per CU.
-template <int PR>
-constexpr int batch_blocks() {
-    return PR == PREC_F64 ? 256 : 512;  // blocks of four waves: one or two per CU
-}
-
+// The step of a batch of lattices of one material: one work item per wave, on a
+// grid of at least a quarter as many blocks as the table has items (the host
+// sizes it; waves beyond the items end at once).  A wave finds its simulation by
+// bisection over the entries' first items (they are in simulation order), and
+// the blocks that carry items are dealt to the XCDs in contiguous runs, as in
+// march_kernel, so that neighbouring strips share their halo lines in one L2.
+// An item's work depends only on its own lattice, so a simulation's results do
+// not depend on its company.  No wave takes a second item: nothing is carried
+// from one item to the next.  FP64 runs one wave per SIMD, as in march_kernel.
 template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
     __shared__ HaloOf<PR, HR> halo_lds[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nsims = step->nsims, nitems = step->nitems;
-    int s = 0;  // the simulation of the current item (items are in simulation order)
-    for (int item = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv); item < nitems;
-         item += gridDim.x * 4) {
-        while (s + 1 < nsims && step->e[s + 1].item0 <= item) s++;
-        const BatchEntry& e = step->e[s];
-        if (e.skip) continue;
-        const int local = item - e.item0;
-        march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
+    const int used = (nitems + 3) / 4;  // blocks that carry items
+    if ((int)blockIdx.x >= used) return;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, used) * 4 + wv);
+    if (item >= nitems) return;
+    int lo = 0, hi = nsims - 1;  // the last entry whose first item is at or before item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (step->e[mid].item0 <= item) lo = mid;
+        else hi = mid - 1;
     }
+    const BatchEntry& e = step->e[lo];
+    if (e.skip) return;
+    const int local = item - e.item0;
+    march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
 }
 
 // ---- per-node helpers for init, read-out, diagnostics and the multi-pass step (FP64) -------
@@ -1492,8 +1493,8 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
 }
 
 template <int PR>
-static void batch_step_p(int material, const BatchStep* step, hipStream_t st) {
-    const dim3 grid(batch_blocks<PR>()), wgrid(kWallBatchBlocks), block(256);
+static void batch_step_p(int material, const BatchStep* step, int blocks, hipStream_t st) {
+    const dim3 grid(blocks), wgrid(kWallBatchBlocks), block(256);
     if (material == MAT_SVK) {
         hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
@@ -1503,12 +1504,12 @@ static void batch_step_p(int material, const BatchStep* step, hipStream_t st) {
     }
 }
 
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, hipStream_t st) {
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st) {
     switch (prec) {
-    case PREC_F64: batch_step_p<PREC_F64>(material, step, st); break;
-    case PREC_F32: batch_step_p<PREC_F32>(material, step, st); break;
-    case PREC_F16: batch_step_p<PREC_F16>(material, step, st); break;
-    default: batch_step_p<PREC_BF16>(material, step, st); break;
+    case PREC_F64: batch_step_p<PREC_F64>(material, step, blocks, st); break;
+    case PREC_F32: batch_step_p<PREC_F32>(material, step, blocks, st); break;
+    case PREC_F16: batch_step_p<PREC_F16>(material, step, blocks, st); break;
+    default: batch_step_p<PREC_BF16>(material, step, blocks, st); break;
     }
     return hipGetLastError();
 }

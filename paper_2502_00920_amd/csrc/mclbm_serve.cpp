@@ -7,10 +7,12 @@
 // (their step arguments: buffers by step parity, wall values at their own step
 // index, work items), uploads the round's tables with one copy, and replays on
 // each of four streams a graph of the group's K launches of the batched step
-// kernel, captured once: the kernel reads its table from device memory and
-// runs on a fixed grid, so one graph serves every batch.  A step of a group
-// lasts about as long as one work item (a march over a chunk of at most 34
-// rows), whatever its size; the groups' steps are independent and run side by
+// kernel: the kernel reads its table from device memory, one work item per
+// wave, so a graph serves every round whose items fit its grid; a round with
+// more items captures the group's graph again on a grid at least twice as
+// large.  A step of a group lasts about as long as one work item (a march over
+// a chunk of at most 34 rows), whatever its size; the groups' steps are
+// independent and run side by
 // side on the hardware queues, so that one group's tail overlaps another's
 // work.  Between rounds the host collects the simulations that have finished (their displacement is copied to the caller's buffer) and
 // admits waiting requests in arrival order while a slot is free and their
@@ -118,6 +120,7 @@ struct mclbm_server {
     std::unordered_map<int64_t, Request> reqs;
     hipStream_t gstream[kGroups] = {};
     hipGraphExec_t graph[kGroups] = {};
+    int graph_blocks[kGroups] = {};  // blocks of the march in each captured graph
     hipEvent_t fork = nullptr, join[kGroups] = {};
     hipEvent_t round_done = nullptr;
     bool in_flight = false;
@@ -185,20 +188,21 @@ int start(mclbm_server* sv, Request& r) {
     return rc;
 }
 
-// the K steps of group gi as one graph, on its stream
-int capture(mclbm_server* sv, int gi) {
+// the K steps of group gi as one graph, on its stream, the march on `blocks` blocks
+int capture(mclbm_server* sv, int gi, int blocks) {
     hipStream_t st = sv->gstream[gi];
     SV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int k = 0; k < sv->cfg.steps_per_round && err == hipSuccess; k++)
         err = launch_batch_step(sv->prec, gi < 2 ? MAT_SVK : MAT_NH,
-                                reinterpret_cast<const BatchStep*>(sv->pool + table_off(sv, k, gi)), st);
+                                reinterpret_cast<const BatchStep*>(sv->pool + table_off(sv, k, gi)), blocks, st);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (err == hipSuccess) err = ec;
     if (err == hipSuccess) err = hipGraphInstantiate(&sv->graph[gi], g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (err != hipSuccess) return set_error(MCLBM_EHIP, hipGetErrorString(err));
+    sv->graph_blocks[gi] = blocks;
     return MCLBM_OK;
 }
 
@@ -377,9 +381,21 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
     std::memset(sv->host_table + sv->flags_off, 0, (size_t)nscan * sizeof(uint32_t));
     // 4. one upload, then the four groups' graphs side by side
     SV_HIP(hipMemcpyAsync(sv->pool, sv->host_table, sv->reserved_bytes, hipMemcpyHostToDevice, sv->stream));
-    for (int g = 0; g < kGroups; g++)
-        if (!sv->graph[g])
-            if (int rc = capture(sv, g)) return rc;
+    // a group's graph serves every round whose tables fit its march grid (one
+    // work item per wave); a larger round captures it again, with a grid twice
+    // as large or more
+    for (int g = 0; g < kGroups; g++) {
+        int most = 0;
+        for (int k = 0; k < K; k++)
+            most = std::max(most, reinterpret_cast<const BatchStep*>(sv->host_table + table_off(sv, k, g))->nitems);
+        const int blocks = batch_march_blocks(most);
+        if (sv->graph[g] && sv->graph_blocks[g] >= blocks) continue;
+        if (sv->graph[g]) {
+            SV_HIP(hipGraphExecDestroy(sv->graph[g]));
+            sv->graph[g] = nullptr;
+        }
+        if (int rc = capture(sv, g, blocks)) return rc;
+    }
     SV_HIP(hipEventRecord(sv->fork, sv->stream));
     for (int g = 0; g < kGroups; g++) {
         SV_HIP(hipStreamWaitEvent(sv->gstream[g], sv->fork, 0));

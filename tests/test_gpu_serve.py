@@ -91,6 +91,61 @@ def test_isolation_bitwise(M, precision):
         del solo
 
 
+def smooth_u0(nx, ny, seed, amp=1e-3):
+    """A smooth nonzero initial displacement, so that every node's update shows
+    in the first step (a work item left out or written elsewhere cannot hide in
+    a region still at rest)."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    u = np.empty((2, ny, nx))
+    for c in range(2):
+        kx, ky = rng.integers(1, 4, size=2)
+        px, py = rng.uniform(0, 2 * np.pi, size=2)
+        u[c] = amp * np.sin(2 * np.pi * kx * x / nx + px) * np.cos(2 * np.pi * ky * y / ny + py)
+    return u
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32", "f16", "bf16"])
+def test_batch_beyond_the_first_grid(M, precision):
+    """Every work item of a large batch is stepped once per step: a first round of
+    small requests, then 32 lattices of 600^2 nodes (180 work items each, about
+    1440 per group), so that the batch march outgrows its first grid and its
+    graphs are captured again; each result against the single-lattice path."""
+    print(f"\n[case] server batch beyond the first grid {precision}", flush=True)
+    small = small_requests(8, seed=11)
+    for r in small:
+        r["nx"] = r["ny"] = 100
+        r["nsteps"] = 4
+    big = small_requests(32, seed=12)
+    for r in big:
+        r["nx"] = r["ny"] = 600
+        r["nsteps"] = 8
+    u0 = {id(r): smooth_u0(r["nx"], r["ny"], seed=i) for i, r in enumerate(small + big)}
+    sv = M.Server(precision=precision, steps_per_round=4, max_active=64, pool_bytes=4 << 30)
+
+    def submit(r):
+        return sv.submit(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
+                         sides=r["sides"], nsteps=r["nsteps"], u0=u0[id(r)])
+    ids = [submit(r) for r in small]
+    done = sv.progress()  # the first round: the small requests only
+    ids += [submit(r) for r in big]
+    while len(done) < len(ids):
+        done += sv.progress()
+    for r, rid in zip(small + big, ids):
+        state, status, u = sv.result(rid)
+        assert state == 2 and status == 0
+        s = M.Sim(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
+                  precision=precision if precision in TOL else "f64")
+        for name, spec in r["sides"].items():
+            s.set_side(name, *((spec,) if isinstance(spec, str) else tuple(spec)))
+        s.init(u0[id(r)])
+        s.step(r["nsteps"])
+        ref = s.read("u")
+        del s
+        e = np.linalg.norm(u - ref) / np.linalg.norm(ref)
+        assert e <= (TOL[precision] if precision in TOL else HALF_U[precision]), (r["nx"], r["case"], e)
+
+
 def test_admission_by_memory(M):
     print("\n[case] server admission by pool size", flush=True)
     reqs = small_requests(6, seed=5)
