@@ -92,8 +92,8 @@ def time_mode(mode: str, n: int, steps: int, warmup: int):
     nodes = n * n
     ms_step = ms / steps
     mlups = nodes * steps / (ms * 1e-3) / 1e6
-    # march_kernel updates every node once per launch (the wall pass after it
-    # redoes the 4 n - 4 wall nodes)
+    # march_kernel updates every node off the walls once per launch (the wall
+    # kernel after it the 4 n - 4 wall nodes)
     alg_bytes = BYTES_PER_LUP[mode] * nodes
     comp_bytes = COMPULSORY_BYTES_PER_LUP[mode] * nodes
     achieved = alg_bytes / (ms_kernel * 1e-3) / 1e9
@@ -106,7 +106,7 @@ def time_mode(mode: str, n: int, steps: int, warmup: int):
                                 "achieved": comp_bytes / (ms_kernel * 1e-3) / 1e9,
                                 "frac": comp_bytes / (ms_kernel * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "kernels": {"march_kernel_ms": ms_kernel, "step_ms_events": ms_steps,
-                    "wall_pass_ms": ms_steps - ms_kernel,
+                    "wall_kernel_ms": ms_steps - ms_kernel,
                     "algorithmic_bytes_per_launch": alg_bytes, "bytes_per_lup": BYTES_PER_LUP[mode],
                     "traffic_vs_algorithmic": None if traffic is None else traffic / alg_bytes,
                     "traffic_vs_compulsory": None if traffic is None else traffic / comp_bytes},

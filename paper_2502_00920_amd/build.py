@@ -25,6 +25,7 @@ FLAGS = [
 
 
 DEMO = os.path.join(PKG, "mclbm_demo")
+PATTERN = os.path.join(PKG, "march_pattern")
 
 
 def build(verbose: bool = False) -> str:
@@ -35,6 +36,7 @@ def build(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     build_demo(verbose)
+    build_pattern(verbose)
     return LIB
 
 
@@ -48,6 +50,19 @@ def build_demo(verbose: bool = False) -> str:
     subprocess.check_call(cmd)
     os.replace(tmp, DEMO)
     return DEMO
+
+
+def build_pattern(verbose: bool = False) -> str:
+    """The march-pattern bandwidth probe (a stand-alone HIP program)."""
+    tmp = PATTERN + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17",
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           os.path.join(CSRC, "march_pattern.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, PATTERN)
+    return PATTERN
 
 
 if __name__ == "__main__":

@@ -428,8 +428,11 @@ ReadArgs read_args(const mclbm_sim* s) {
     return a;
 }
 
-// one step on the stream: march_kernel and the wall pass (the event, when set,
-// is recorded between them), or the three passes of the multi-pass step
+// one step on the stream: march_kernel, then the wall kernel (the event, when
+// set, is recorded between them; the wall kernel on a stream of its own beside
+// the march made the 8192^2 step 2 % slower in FP32 and halved the step rate of
+// small lattices, whose steps last tens of microseconds), or the three passes
+// of the multi-pass step
 hipError_t launch_one_step(mclbm_sim* s, hipEvent_t between = nullptr) {
     const StepArgs a = step_args(s);
     if (!s->L.multipass) {
@@ -581,7 +584,7 @@ void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e) {
     e->a.w = walls_at(s, s->n + k);
     march_shape(s->g, &e->nstrip, &e->nchunk, &e->chunk);
     e->skip = 0;
-    e->pad_ = 0;
+    e->seg0 = 0;
 }
 
 void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e) {

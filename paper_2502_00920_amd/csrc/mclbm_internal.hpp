@@ -60,21 +60,43 @@ struct PassArgs {
     const double* sig_c;    // sigma of the collision at t_n (sigma_n, or sigma_{n-1})
 };
 
+// The wall segments of a lattice: the nodes on its non-periodic sides (rows 0
+// and ny - 1 whole, columns 0 and nx - 1 between them) in runs of kWallSeg along
+// each side, one block per run (the wall rules of Sect. 3.3 in FP64; the march
+// stores nothing there).
+constexpr int kWallSeg = 256;
+struct WallSegs {
+    int nrow, ncol;  // segments per row side, per column side
+    int total;
+};
+__host__ __device__ __forceinline__ WallSegs wall_segs(const Geometry& g) {
+    WallSegs w;
+    w.nrow = g.py ? 0 : (g.nx + kWallSeg - 1) / kWallSeg;
+    const int h = g.py ? g.ny : g.ny - 2;
+    w.ncol = g.px ? 0 : (h + kWallSeg - 1) / kWallSeg;
+    w.total = 2 * w.nrow + 2 * w.ncol;
+    return w;
+}
+// blocks of a step launch given to wall segments: rounded up to a multiple of
+// the 8 XCDs, so that the march blocks after them keep their XCD order
+__host__ __device__ __forceinline__ int wall_blocks(int nseg) { return (nseg + 7) / 8 * 8; }
+
 // One simulation's share of one step of a batch: its step arguments, its work
-// items [item0, item0 + nstrip * nchunk) and whether it sits the step out (it
-// has finished its steps in this round).
+// items [item0, item0 + nstrip * nchunk), its wall segments [seg0, seg0 +
+// wall_segs(a.g).total) and whether it sits the step out (it has finished its
+// steps in this round).
 struct BatchEntry {
     StepArgs a;
     int nstrip, nchunk, chunk;
     int item0;
     int skip;
-    int pad_;
+    int seg0;
 };
 
 // One step of a batch for one material: the simulations in item order.
 struct BatchStep {
-    int nsims, nitems;
-    int pad_[2];
+    int nsims, nitems, nsegs;
+    int pad_;
     BatchEntry e[1];  // nsims entries (the table is allocated for the batch's maximum)
 };
 inline size_t batch_step_bytes(int max_sims) {
@@ -97,17 +119,18 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 // work items of one lattice's step in a batch: 64-column strips times row chunks
 void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk);
 // the step for every simulation of one material in the table at step (device
-// memory, read by the kernel): the march on `blocks` blocks of four waves, one
-// work item per wave, so blocks * 4 must cover the table's items (extra waves
-// end at once); the wall pass on a fixed grid.  Graph-capturable: a captured
-// launch serves any table whose items fit its blocks.
+// memory, read by the kernel), as one launch of `blocks` blocks: first one
+// block per wall segment of the table, then one wave per work item, so blocks
+// must cover wall_blocks(nsegs) + nitems / 4 (extra blocks end at once).
+// Graph-capturable: a captured launch serves any table that fits its blocks.
 hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st);
-// blocks of the batch march for a table of n items: a quarter of n rounded up
-// to a power of two, at least kMinBatchBlocks (so that a captured launch is
-// re-captured only when a batch outgrows it by a factor of two)
+// blocks of the batch step for a table of nitems items and nsegs wall
+// segments: what they need, rounded up to a power of two and at least
+// kMinBatchBlocks (so that a captured launch is re-captured only when a batch
+// outgrows it by a factor of two)
 constexpr int kMinBatchBlocks = 256;
-inline int batch_march_blocks(long long n) {
-    long long need = (n + 3) / 4, b = kMinBatchBlocks;
+inline int batch_blocks(long long nitems, long long nsegs) {
+    long long need = wall_blocks((int)nsegs) + (nitems + 3) / 4, b = kMinBatchBlocks;
     while (b < need) b *= 2;
     return (int)b;
 }
@@ -129,8 +152,9 @@ int set_error(int code, const char* msg);
 int check_side_program(const void* spec);
 
 // prec: PREC_F64 / F32 / F16 / BF16.  The fused step: march_kernel over every
-// node (launch_step), then the wall pass that redoes the nodes on non-periodic
-// sides with the wall rules (launch_walls; nothing for a periodic lattice).
+// node off the non-periodic sides (launch_step), then the wall kernel for the
+// nodes on them, with the wall rules in FP64 (launch_walls; nothing for a
+// periodic lattice).
 hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st);
 hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st);
 // the multi-pass step: stresses, source, step (three launches)

@@ -701,8 +701,11 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             T fn[9];
 #pragma unroll
             for (int q = 0; q < 9; q++) fn[q] = T(fnd[q]);
-            // the two rows that prime the chunk store nothing (wave-uniform)
-            if (r >= yc && r < ye)
+            // the two rows that prime the chunk store nothing, and nor do the
+            // rows and lanes on non-periodic sides: the wall blocks of the same
+            // launch write those nodes (rows wave-uniform; lanes only in the
+            // edge copy of the loop)
+            if (r >= yc && r < ye && !lo_row(r) && !hi_row(r) && !atL && !atR)
                 store_node((uint32_t)(r * g.pitch + vx), U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
                            U0[1] + a.k.ucoef * (m1y + o1y + (double)G0[1]), fn);
 
@@ -764,52 +767,6 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         if (two_rates) run(Flag<true>{}, Flag<true>{});
         else run(Flag<true>{}, Flag<false>{});
     }
-}
-
-// The step of one lattice: one work item per wave.  Two waves per SIMD, but one
-// in FP64: its loop needs about 306 registers, and at two waves (256 each) the
-// 50 spilled to scratch cost more than the halved occupancy (8192^2 tension:
-// 26.9k MLUPS at two waves, 28.4k at one).
-template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(StepArgs a, int nstrip, int nchunk,
-                                                                             int chunk) {
-    __shared__ HaloOf<PR, HR> halo_lds[4];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
-    if (item >= nstrip * nchunk) return;
-    march_item<PR, MAT, HR, D>(a, halo_lds[wv], lane, item % nstrip, item / nstrip, chunk);
-}
-
-// The step of a batch of lattices of one material: one work item per wave, on a
-// grid of at least a quarter as many blocks as the table has items (the host
-// sizes it; waves beyond the items end at once).  A wave finds its simulation by
-// bisection over the entries' first items (they are in simulation order), and
-// the blocks that carry items are dealt to the XCDs in contiguous runs, as in
-// march_kernel, so that neighbouring strips share their halo lines in one L2.
-// An item's work depends only on its own lattice, so a simulation's results do
-// not depend on its company.  No wave takes a second item: nothing is carried
-// from one item to the next.  FP64 runs one wave per SIMD, as in march_kernel.
-template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
-    __shared__ HaloOf<PR, HR> halo_lds[4];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int nsims = step->nsims, nitems = step->nitems;
-    const int used = (nitems + 3) / 4;  // blocks that carry items
-    if ((int)blockIdx.x >= used) return;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, used) * 4 + wv);
-    if (item >= nitems) return;
-    int lo = 0, hi = nsims - 1;  // the last entry whose first item is at or before item
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (step->e[mid].item0 <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchEntry& e = step->e[lo];
-    if (e.skip) return;
-    const int local = item - e.item0;
-    march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
 }
 
 // ---- per-node helpers for init, read-out, diagnostics and the multi-pass step (FP64) -------
@@ -1243,35 +1200,22 @@ __global__ __launch_bounds__(256) void pass_step_kernel(PassArgs pa) {
     node_update<PR, TWO_RATES>(a, gx, gy, sig_c, sig_n, Tw);
 }
 
-// ---- the wall pass of the fused step ------------------------------------------------------
+// ---- the wall blocks of the fused step ----------------------------------------------------
 //
-// march_kernel leaves the nodes on non-periodic sides with pulls from beyond the
-// wall; this pass redoes their whole update in FP64 (node_update: the walls of
-// Sect. 3.3 with T and sigma of u_n, first-order boundary differences), after
-// march_kernel on the same stream.  A block takes a segment of kWallSeg nodes of
-// one side (the rows 0 and ny - 1 of non-periodic y sides whole, the columns 0
-// and nx - 1 of non-periodic x sides between them): it computes T on the three
-// node lines nearest the wall and sigma on the two nearest into LDS, then one
-// thread per wall node updates it from those.
+// The march stores nothing at the nodes on non-periodic sides; wall blocks
+// update them in FP64 (node_update: the walls of Sect. 3.3 with T and sigma of
+// u_n, first-order boundary differences): wall_kernel after march_kernel, or
+// blocks of the batched step's own launch (both kinds read only level n, so
+// they run side by side there).  A wall block takes a segment of
+// kWallSeg nodes of one side (the rows 0 and ny - 1 of non-periodic y sides
+// whole, the columns 0 and nx - 1 of non-periodic x sides between them): it
+// computes T on the three node lines nearest the wall and sigma on the two
+// nearest into LDS, then one thread per wall node updates it from those.
 
-constexpr int kWallSeg = 256;
 struct WallBand {
     double T[3][kWallSeg + 4][4];  // [distance from the wall][along, from start - 2][comp]
     double S[2][kWallSeg + 2][2];  // [distance][along, from start - 1][comp]
 };
-
-struct WallSegs {
-    int nrow, ncol;  // segments per row side, per column side
-    int total;
-};
-__host__ __device__ __forceinline__ WallSegs wall_segs(const Geometry& g) {
-    WallSegs w;
-    w.nrow = g.py ? 0 : (g.nx + kWallSeg - 1) / kWallSeg;
-    const int h = g.py ? g.ny : g.ny - 2;
-    w.ncol = g.px ? 0 : (h + kWallSeg - 1) / kWallSeg;
-    w.total = 2 * w.nrow + 2 * w.ncol;
-    return w;
-}
 
 template <int PR, int MAT>
 __device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
@@ -1354,32 +1298,88 @@ __device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
     else node_update<PR, false>(a, gx, gy, Sband, sig_n, Tband);
 }
 
+// A wall block's work out of line, for the batched step: inlined there, its
+// FP64 wall rules made the compiler spill in the march's code too.
+template <int PR, int MAT>
+__device__ __noinline__ void wall_block(const StepArgs& a, int seg, WallBand& band) {
+    wall_segment<PR, MAT>(a, seg, band);
+}
+
+// LDS of a step block: the four waves' halo blocks, or a wall segment's band
+template <int PR, int HR>
+union StepLds {
+    HaloOf<PR, HR> halo[4];
+    WallBand band;
+};
+
+// The step of one lattice: one work item per wave (the nodes on non-periodic
+// sides are left to wall_kernel, launched after it).  Two waves per SIMD, but
+// one in FP64: its loop needs about 306 registers, and at two waves (256 each)
+// the 50 spilled to scratch cost more than the halved occupancy (8192^2
+// tension: 26.9k MLUPS at two waves, 28.4k at one).
+template <int PR, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(StepArgs a, int nstrip, int nchunk,
+                                                                             int chunk) {
+    __shared__ HaloOf<PR, HR> halo_lds[4];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
+    if (item >= nstrip * nchunk) return;
+    march_item<PR, MAT, HR, D>(a, halo_lds[wv], lane, item % nstrip, item / nstrip, chunk);
+}
+
+// The wall segments of one lattice, one block each, after march_kernel on the
+// same stream.  (Fused into march_kernel's launch, the wall blocks held their
+// slots at the start of the march: 8192^2 tension ran the same in FP32 and 2 %
+// slower in FP16.  A batch fuses them, where they shorten every step.)
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
     __shared__ WallBand band;
     wall_segment<PR, MAT>(a, blockIdx.x, band);
 }
 
-// the wall pass of every simulation in a batch table, on a fixed grid: block b
-// takes the segments b, b + grid, ... of the table's simulations in order
-constexpr int kWallBatchBlocks = 256;
-template <int PR, int MAT>
-__global__ __launch_bounds__(256) void wall_batch_kernel(const BatchStep* __restrict__ step) {
-    __shared__ WallBand band;
-    const int nsims = step->nsims;
-    int base = 0;  // segments of the simulations before s
-    for (int s = 0; s < nsims; s++) {
-        const BatchEntry& e = step->e[s];
-        const int n = e.skip ? 0 : wall_segs(e.a.g).total;
-        // the first of this block's segments at or after base
-        int k = (int)blockIdx.x - base % (int)gridDim.x;
-        if (k < 0) k += gridDim.x;
-        for (; k < n; k += gridDim.x) {
-            wall_segment<PR, MAT>(e.a, k, band);
-            __syncthreads();  // the band is reused by the next segment
+// The step of a batch of lattices of one material in one launch: first one
+// block per wall segment of the table (wall_blocks of their number), then one
+// work item per wave, on a grid the host sizes to cover both (extra blocks end
+// at once).  A block finds its simulation by bisection over the entries' first
+// segments or items (they are in simulation order), and the blocks that carry
+// items are dealt to the XCDs in contiguous runs, as in march_kernel, so that
+// neighbouring strips share their halo lines in one L2.  A simulation's blocks
+// read only its own buffers, so its results do not depend on its company.  No
+// wave takes a second item: nothing is carried from one item to the next.
+template <int PR, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
+    __shared__ StepLds<PR, HR> lds;
+    const int nsims = step->nsims, nitems = step->nitems, nsegs = step->nsegs;
+    const int nwall = wall_blocks(nsegs);
+    // the last entry whose first segment (wall) or item (march) is at or before k
+    auto find = [&](int k, bool wall) {
+        int lo = 0, hi = nsims - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if ((wall ? step->e[mid].seg0 : step->e[mid].item0) <= k) lo = mid;
+            else hi = mid - 1;
         }
-        base += n;
+        return lo;
+    };
+    if ((int)blockIdx.x < nwall) {
+        const int seg = blockIdx.x;
+        if (seg >= nsegs) return;
+        const BatchEntry& e = step->e[find(seg, true)];
+        if (!e.skip) wall_block<PR, MAT>(e.a, seg - e.seg0, lds.band);
+        return;
     }
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int used = (nitems + 3) / 4;  // blocks that carry items
+    const int b = (int)blockIdx.x - nwall;
+    if (b >= used) return;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(b, used) * 4 + wv);
+    if (item >= nitems) return;
+    const BatchEntry& e = step->e[find(item, false)];
+    if (e.skip) return;
+    const int local = item - e.item0;
+    march_item<PR, MAT, HR, D>(e.a, lds.halo[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
 }
 
 hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st) {
@@ -1480,40 +1480,6 @@ static void launch_march(const StepArgs& a, hipStream_t st) {
                        nstrip, nchunk, chunk);
 }
 
-// In a batch the other lattices supply the waves: chunks of 34 rows (or the
-// whole height, if less).  A step of a batch lasts about one chunk's march, so
-// shorter chunks end it sooner, at the price of the two rows that prime each
-// chunk; 34 rows gave the highest throughput on the serving mix (64: -9 %,
-// 22: even, 10: -9 %).
-void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
-    *nstrip = g.pitch / 64;
-    const int m = std::min(6, (g.ny + 2 + 5) / 6);
-    *chunk = 6 * m - 2;
-    *nchunk = (g.ny + *chunk - 1) / *chunk;
-}
-
-template <int PR>
-static void batch_step_p(int material, const BatchStep* step, int blocks, hipStream_t st) {
-    const dim3 grid(blocks), wgrid(kWallBatchBlocks), block(256);
-    if (material == MAT_SVK) {
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
-    } else {
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), grid, block, 0, st, step);
-        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_NH>), wgrid, block, 0, st, step);
-    }
-}
-
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st) {
-    switch (prec) {
-    case PREC_F64: batch_step_p<PREC_F64>(material, step, blocks, st); break;
-    case PREC_F32: batch_step_p<PREC_F32>(material, step, blocks, st); break;
-    case PREC_F16: batch_step_p<PREC_F16>(material, step, blocks, st); break;
-    default: batch_step_p<PREC_BF16>(material, step, blocks, st); break;
-    }
-    return hipGetLastError();
-}
-
 template <int PR, int MAT>
 static void launch_walls_pm(const StepArgs& a, hipStream_t st) {
     const int nseg = wall_segs(a.g).total;
@@ -1537,6 +1503,36 @@ hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t s
     case PREC_F16: return walls_p<PREC_F16>(material, a, st);
     default: return walls_p<PREC_BF16>(material, a, st);
     }
+}
+
+// In a batch the other lattices supply the waves: chunks of 34 rows (or the
+// whole height, if less).  A step of a batch lasts about one chunk's march, so
+// shorter chunks end it sooner, at the price of the two rows that prime each
+// chunk; 34 rows gave the highest throughput on the serving mix (64: -9 %,
+// 22: even, 10: -9 %).
+void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
+    *nstrip = g.pitch / 64;
+    const int m = std::min(6, (g.ny + 2 + 5) / 6);
+    *chunk = 6 * m - 2;
+    *nchunk = (g.ny + *chunk - 1) / *chunk;
+}
+
+template <int PR>
+static void batch_step_p(int material, const BatchStep* step, int blocks, hipStream_t st) {
+    if (material == MAT_SVK)
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), dim3(blocks), dim3(256), 0, st, step);
+    else
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), dim3(blocks), dim3(256), 0, st, step);
+}
+
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st) {
+    switch (prec) {
+    case PREC_F64: batch_step_p<PREC_F64>(material, step, blocks, st); break;
+    case PREC_F32: batch_step_p<PREC_F32>(material, step, blocks, st); break;
+    case PREC_F16: batch_step_p<PREC_F16>(material, step, blocks, st); break;
+    default: batch_step_p<PREC_BF16>(material, step, blocks, st); break;
+    }
+    return hipGetLastError();
 }
 
 template <int PR>

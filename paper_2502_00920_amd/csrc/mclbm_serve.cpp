@@ -345,6 +345,7 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
             BatchStep* st = reinterpret_cast<BatchStep*>(sv->host_table + table_off(sv, k, g));
             st->nsims = 0;
             st->nitems = 0;
+            st->nsegs = 0;
         }
     // groups: largest lattices first, each to the lighter of its material's two
     std::vector<int64_t> order(sv->active);
@@ -366,6 +367,8 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
             batch_entry(r.sim, k, &e);
             e.item0 = st->nitems;
             st->nitems += e.nstrip * e.nchunk;
+            e.seg0 = st->nsegs;
+            st->nsegs += wall_segs(e.a.g).total;
         }
     }
     // the failure scan of every simulation's displacement after the round; its
@@ -381,14 +384,15 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
     std::memset(sv->host_table + sv->flags_off, 0, (size_t)nscan * sizeof(uint32_t));
     // 4. one upload, then the four groups' graphs side by side
     SV_HIP(hipMemcpyAsync(sv->pool, sv->host_table, sv->reserved_bytes, hipMemcpyHostToDevice, sv->stream));
-    // a group's graph serves every round whose tables fit its march grid (one
-    // work item per wave); a larger round captures it again, with a grid twice
-    // as large or more
+    // a group's graph serves every round whose tables fit its grid (a block per
+    // wall segment, a wave per work item); a larger round captures it again,
+    // with a grid twice as large or more
     for (int g = 0; g < kGroups; g++) {
-        int most = 0;
-        for (int k = 0; k < K; k++)
-            most = std::max(most, reinterpret_cast<const BatchStep*>(sv->host_table + table_off(sv, k, g))->nitems);
-        const int blocks = batch_march_blocks(most);
+        int blocks = 0;
+        for (int k = 0; k < K; k++) {
+            const BatchStep* t = reinterpret_cast<const BatchStep*>(sv->host_table + table_off(sv, k, g));
+            blocks = std::max(blocks, batch_blocks(t->nitems, t->nsegs));
+        }
         if (sv->graph[g] && sv->graph_blocks[g] >= blocks) continue;
         if (sv->graph[g]) {
             SV_HIP(hipGraphExecDestroy(sv->graph[g]));
