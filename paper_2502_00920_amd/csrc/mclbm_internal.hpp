@@ -64,7 +64,7 @@ struct PassArgs {
 // and ny - 1 whole, columns 0 and nx - 1 between them) in runs of kWallSeg along
 // each side, one block per run (the wall rules of Sect. 3.3 in FP64; the march
 // stores nothing there).
-constexpr int kWallSeg = 256;
+constexpr int kWallSeg = 64;
 struct WallSegs {
     int nrow, ncol;  // segments per row side, per column side
     int total;
@@ -77,9 +77,6 @@ __host__ __device__ __forceinline__ WallSegs wall_segs(const Geometry& g) {
     w.total = 2 * w.nrow + 2 * w.ncol;
     return w;
 }
-// blocks of a step launch given to wall segments: rounded up to a multiple of
-// the 8 XCDs, so that the march blocks after them keep their XCD order
-__host__ __device__ __forceinline__ int wall_blocks(int nseg) { return (nseg + 7) / 8 * 8; }
 
 // One simulation's share of one step of a batch: its step arguments, its work
 // items [item0, item0 + nstrip * nchunk), its wall segments [seg0, seg0 +
@@ -119,18 +116,19 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 // work items of one lattice's step in a batch: 64-column strips times row chunks
 void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk);
 // the step for every simulation of one material in the table at step (device
-// memory, read by the kernel), as one launch of `blocks` blocks: first one
-// block per wall segment of the table, then one wave per work item, so blocks
-// must cover wall_blocks(nsegs) + nitems / 4 (extra blocks end at once).
-// Graph-capturable: a captured launch serves any table that fits its blocks.
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st);
-// blocks of the batch step for a table of nitems items and nsegs wall
-// segments: what they need, rounded up to a power of two and at least
-// kMinBatchBlocks (so that a captured launch is re-captured only when a batch
-// outgrows it by a factor of two)
+// memory, read by the kernels): the march on march_blocks blocks of four
+// waves, one work item per wave, then the wall segments on wall_blocks
+// blocks, one segment each; the grids must cover the table's items / 4 and
+// segments (extra blocks end at once).  Graph-capturable: a captured launch
+// serves any table that fits its grids.
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int march_blocks, int wall_blocks,
+                             hipStream_t st);
+// a grid of at least `need` blocks: a power of two, at least kMinBatchBlocks
+// (so that a captured launch is re-captured only when a batch outgrows it by a
+// factor of two)
 constexpr int kMinBatchBlocks = 256;
-inline int batch_blocks(long long nitems, long long nsegs) {
-    long long need = wall_blocks((int)nsegs) + (nitems + 3) / 4, b = kMinBatchBlocks;
+inline int batch_grid(long long need) {
+    long long b = kMinBatchBlocks;
     while (b < need) b *= 2;
     return (int)b;
 }

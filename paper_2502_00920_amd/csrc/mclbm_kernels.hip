@@ -1204,9 +1204,8 @@ __global__ __launch_bounds__(256) void pass_step_kernel(PassArgs pa) {
 //
 // The march stores nothing at the nodes on non-periodic sides; wall blocks
 // update them in FP64 (node_update: the walls of Sect. 3.3 with T and sigma of
-// u_n, first-order boundary differences): wall_kernel after march_kernel, or
-// blocks of the batched step's own launch (both kinds read only level n, so
-// they run side by side there).  A wall block takes a segment of
+// u_n, first-order boundary differences), launched after the march on the same
+// stream (wall_kernel, wall_batch_kernel).  A wall block takes a segment of
 // kWallSeg nodes of one side (the rows 0 and ny - 1 of non-periodic y sides
 // whole, the columns 0 and nx - 1 of non-periodic x sides between them): it
 // computes T on the three node lines nearest the wall and sigma on the two
@@ -1298,20 +1297,6 @@ __device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
     else node_update<PR, false>(a, gx, gy, Sband, sig_n, Tband);
 }
 
-// A wall block's work out of line, for the batched step: inlined there, its
-// FP64 wall rules made the compiler spill in the march's code too.
-template <int PR, int MAT>
-__device__ __noinline__ void wall_block(const StepArgs& a, int seg, WallBand& band) {
-    wall_segment<PR, MAT>(a, seg, band);
-}
-
-// LDS of a step block: the four waves' halo blocks, or a wall segment's band
-template <int PR, int HR>
-union StepLds {
-    HaloOf<PR, HR> halo[4];
-    WallBand band;
-};
-
 // The step of one lattice: one work item per wave (the nodes on non-periodic
 // sides are left to wall_kernel, launched after it).  Two waves per SIMD, but
 // one in FP64: its loop needs about 306 registers, and at two waves (256 each)
@@ -1331,55 +1316,63 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
 // The wall segments of one lattice, one block each, after march_kernel on the
 // same stream.  (Fused into march_kernel's launch, the wall blocks held their
 // slots at the start of the march: 8192^2 tension ran the same in FP32 and 2 %
-// slower in FP16.  A batch fuses them, where they shorten every step.)
+// slower in FP16.)
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
     __shared__ WallBand band;
     wall_segment<PR, MAT>(a, blockIdx.x, band);
 }
 
-// The step of a batch of lattices of one material in one launch: first one
-// block per wall segment of the table (wall_blocks of their number), then one
-// work item per wave, on a grid the host sizes to cover both (extra blocks end
-// at once).  A block finds its simulation by bisection over the entries' first
-// segments or items (they are in simulation order), and the blocks that carry
-// items are dealt to the XCDs in contiguous runs, as in march_kernel, so that
-// neighbouring strips share their halo lines in one L2.  A simulation's blocks
-// read only its own buffers, so its results do not depend on its company.  No
-// wave takes a second item: nothing is carried from one item to the next.
+// The step of a batch of lattices of one material: one work item per wave, on
+// a grid the host sizes to cover the table's items (extra waves end at once).
+// A wave finds its simulation by bisection over the entries' first items (they
+// are in simulation order), and the blocks that carry items are dealt to the
+// XCDs in contiguous runs, as in march_kernel, so that neighbouring strips
+// share their halo lines in one L2.  A simulation's waves read only its own
+// buffers, so its results do not depend on its company.  No wave takes a
+// second item: nothing is carried from one item to the next.  (With the wall
+// blocks in the same launch, ahead of the march, the batched step ran 35 %
+// longer on the serving mix: its march needs about one round of resident
+// blocks, and the wall blocks' slots pushed it into a second.)
 template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
-    __shared__ StepLds<PR, HR> lds;
-    const int nsims = step->nsims, nitems = step->nitems, nsegs = step->nsegs;
-    const int nwall = wall_blocks(nsegs);
-    // the last entry whose first segment (wall) or item (march) is at or before k
-    auto find = [&](int k, bool wall) {
-        int lo = 0, hi = nsims - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) / 2;
-            if ((wall ? step->e[mid].seg0 : step->e[mid].item0) <= k) lo = mid;
-            else hi = mid - 1;
-        }
-        return lo;
-    };
-    if ((int)blockIdx.x < nwall) {
-        const int seg = blockIdx.x;
-        if (seg >= nsegs) return;
-        const BatchEntry& e = step->e[find(seg, true)];
-        if (!e.skip) wall_block<PR, MAT>(e.a, seg - e.seg0, lds.band);
-        return;
-    }
+    __shared__ HaloOf<PR, HR> halo_lds[4];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
+    const int nsims = step->nsims, nitems = step->nitems;
     const int used = (nitems + 3) / 4;  // blocks that carry items
-    const int b = (int)blockIdx.x - nwall;
-    if (b >= used) return;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(b, used) * 4 + wv);
+    if ((int)blockIdx.x >= used) return;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, used) * 4 + wv);
     if (item >= nitems) return;
-    const BatchEntry& e = step->e[find(item, false)];
+    int lo = 0, hi = nsims - 1;  // the last entry whose first item is at or before item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (step->e[mid].item0 <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchEntry& e = step->e[lo];
     if (e.skip) return;
     const int local = item - e.item0;
-    march_item<PR, MAT, HR, D>(e.a, lds.halo[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
+    march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
+}
+
+// The wall segments of every simulation in a batch table, one block each, after
+// march_batch_kernel on the same stream, on a grid the host sizes to cover the
+// table's segments (extra blocks end at once); a block finds its simulation by
+// bisection over the entries' first segments.
+template <int PR, int MAT>
+__global__ __launch_bounds__(256) void wall_batch_kernel(const BatchStep* __restrict__ step) {
+    __shared__ WallBand band;
+    const int nsims = step->nsims, seg = blockIdx.x;
+    if (seg >= step->nsegs) return;
+    int lo = 0, hi = nsims - 1;  // the last entry whose first segment is at or before seg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (step->e[mid].seg0 <= seg) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchEntry& e = step->e[lo];
+    if (!e.skip) wall_segment<PR, MAT>(e.a, seg - e.seg0, band);
 }
 
 hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st) {
@@ -1518,19 +1511,24 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
 }
 
 template <int PR>
-static void batch_step_p(int material, const BatchStep* step, int blocks, hipStream_t st) {
-    if (material == MAT_SVK)
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), dim3(blocks), dim3(256), 0, st, step);
-    else
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), dim3(blocks), dim3(256), 0, st, step);
+static void batch_step_p(int material, const BatchStep* step, int march_blocks, int wall_blocks, hipStream_t st) {
+    const dim3 grid(march_blocks), wgrid(wall_blocks), block(256);
+    if (material == MAT_SVK) {
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
+        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
+    } else {
+        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), grid, block, 0, st, step);
+        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_NH>), wgrid, block, 0, st, step);
+    }
 }
 
-hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int blocks, hipStream_t st) {
+hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int march_blocks, int wall_blocks,
+                             hipStream_t st) {
     switch (prec) {
-    case PREC_F64: batch_step_p<PREC_F64>(material, step, blocks, st); break;
-    case PREC_F32: batch_step_p<PREC_F32>(material, step, blocks, st); break;
-    case PREC_F16: batch_step_p<PREC_F16>(material, step, blocks, st); break;
-    default: batch_step_p<PREC_BF16>(material, step, blocks, st); break;
+    case PREC_F64: batch_step_p<PREC_F64>(material, step, march_blocks, wall_blocks, st); break;
+    case PREC_F32: batch_step_p<PREC_F32>(material, step, march_blocks, wall_blocks, st); break;
+    case PREC_F16: batch_step_p<PREC_F16>(material, step, march_blocks, wall_blocks, st); break;
+    default: batch_step_p<PREC_BF16>(material, step, march_blocks, wall_blocks, st); break;
     }
     return hipGetLastError();
 }

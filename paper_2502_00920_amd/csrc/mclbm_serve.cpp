@@ -120,7 +120,7 @@ struct mclbm_server {
     std::unordered_map<int64_t, Request> reqs;
     hipStream_t gstream[kGroups] = {};
     hipGraphExec_t graph[kGroups] = {};
-    int graph_blocks[kGroups] = {};  // blocks of the march in each captured graph
+    int graph_march[kGroups] = {}, graph_wall[kGroups] = {};  // grids of each captured graph
     hipEvent_t fork = nullptr, join[kGroups] = {};
     hipEvent_t round_done = nullptr;
     bool in_flight = false;
@@ -188,21 +188,23 @@ int start(mclbm_server* sv, Request& r) {
     return rc;
 }
 
-// the K steps of group gi as one graph, on its stream, the march on `blocks` blocks
-int capture(mclbm_server* sv, int gi, int blocks) {
+// the K steps of group gi as one graph, on its stream, on grids of the given blocks
+int capture(mclbm_server* sv, int gi, int march_blocks, int wall_blocks) {
     hipStream_t st = sv->gstream[gi];
     SV_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t err = hipSuccess;
     for (int k = 0; k < sv->cfg.steps_per_round && err == hipSuccess; k++)
         err = launch_batch_step(sv->prec, gi < 2 ? MAT_SVK : MAT_NH,
-                                reinterpret_cast<const BatchStep*>(sv->pool + table_off(sv, k, gi)), blocks, st);
+                                reinterpret_cast<const BatchStep*>(sv->pool + table_off(sv, k, gi)), march_blocks,
+                                wall_blocks, st);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(st, &g);
     if (err == hipSuccess) err = ec;
     if (err == hipSuccess) err = hipGraphInstantiate(&sv->graph[gi], g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (err != hipSuccess) return set_error(MCLBM_EHIP, hipGetErrorString(err));
-    sv->graph_blocks[gi] = blocks;
+    sv->graph_march[gi] = march_blocks;
+    sv->graph_wall[gi] = wall_blocks;
     return MCLBM_OK;
 }
 
@@ -384,21 +386,22 @@ MCLBM_EXPORT int mclbm_server_progress(mclbm_server* sv, int64_t* done_ids, int3
     std::memset(sv->host_table + sv->flags_off, 0, (size_t)nscan * sizeof(uint32_t));
     // 4. one upload, then the four groups' graphs side by side
     SV_HIP(hipMemcpyAsync(sv->pool, sv->host_table, sv->reserved_bytes, hipMemcpyHostToDevice, sv->stream));
-    // a group's graph serves every round whose tables fit its grid (a block per
-    // wall segment, a wave per work item); a larger round captures it again,
-    // with a grid twice as large or more
+    // a group's graph serves every round whose tables fit its grids (a wave per
+    // work item, a block per wall segment); a larger round captures it again,
+    // with grids twice as large or more
     for (int g = 0; g < kGroups; g++) {
-        int blocks = 0;
+        int mb = 0, wb = 0;
         for (int k = 0; k < K; k++) {
             const BatchStep* t = reinterpret_cast<const BatchStep*>(sv->host_table + table_off(sv, k, g));
-            blocks = std::max(blocks, batch_blocks(t->nitems, t->nsegs));
+            mb = std::max(mb, batch_grid((t->nitems + 3) / 4));
+            wb = std::max(wb, batch_grid(t->nsegs));
         }
-        if (sv->graph[g] && sv->graph_blocks[g] >= blocks) continue;
+        if (sv->graph[g] && sv->graph_march[g] >= mb && sv->graph_wall[g] >= wb) continue;
         if (sv->graph[g]) {
             SV_HIP(hipGraphExecDestroy(sv->graph[g]));
             sv->graph[g] = nullptr;
         }
-        if (int rc = capture(sv, g, blocks)) return rc;
+        if (int rc = capture(sv, g, std::max(mb, sv->graph_march[g]), std::max(wb, sv->graph_wall[g]))) return rc;
     }
     SV_HIP(hipEventRecord(sv->fork, sv->stream));
     for (int g = 0; g < kGroups; g++) {
