@@ -19,16 +19,23 @@ nu near 0; they are reported as unstable and left out of the latency figures.
 
   python -m paper_2502_00920_amd.serve [--requests 1000] [--seed 0]
       [--steps-min 1000] [--steps-max 20000] [--load 0.8] [--baseline 40]
-prints one JSON line: batched capacity (lattice updates run per second, and
-requests per second), open-loop p50/p99 latency with Poisson arrivals at the
-given fraction of that request rate, and the throughput of one-at-a-time FP64
-solves.
+prints one JSON line: the stream batched with FP32, FP64 and FP16 population
+storage, all requests queued at once (updates run per second, updates of the
+requests that finished stably per second, requests per second, and the
+unstable requests, beyond the CFL bound nu > 1/4 and within it); open-loop
+p50/p99 latency with Poisson arrivals at the given fraction of the FP32 request
+rate; one-at-a-time plain FP64 solves of a sample spread evenly over the
+stream's work per request (checked every 500 steps, so that diverging runs stop
+early as in the server); the gains of batching (batched FP64 over one at a
+time) and of FP32 storage; and each batched format's error against the
+one-at-a-time FP64 results on the sample's stable requests.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import math
+import sys
 import time
 
 import numpy as np
@@ -73,7 +80,7 @@ def _submit(server, r):
 def run_closed(reqs, precision="f32", **server_kw):
     """Every request queued at once: the server's capacity in lattice updates
     run per second (unstable requests stop early and count only the steps they
-    ran)."""
+    ran), and in updates of the requests that finished stably per second."""
     import torch
     from . import mclbm
     sv = mclbm.Server(precision=precision, **server_kw)
@@ -83,9 +90,20 @@ def run_closed(reqs, precision="f32", **server_kw):
     dt = time.perf_counter() - t0
     res = {i: sv.result(rid) for i, rid in enumerate(ids)}
     ran = sum(r["nx"] * r["ny"] * sv.steps(rid) for r, rid in zip(reqs, ids))
+    stable = sum(r["nx"] * r["ny"] * r["nsteps"] for i, r in enumerate(reqs) if res[i][1] == 0)
     del sv
     torch.cuda.empty_cache()
-    return ran / dt, dt, res
+    return {"capacity_lups_per_s": ran / dt, "completed_lups_per_s": stable / dt, "closed_loop_seconds": dt,
+            "requests_per_s": len(reqs) / dt, **unstable_counts(reqs, {i: v[1] for i, v in res.items()})}, res
+
+
+def unstable_counts(reqs, status):
+    """Requests that lost stability (status != 0), beyond the CFL bound of
+    first-order boundary stencils (nu > 1/4, Sect. 3.2) and within it."""
+    bad = [r for r in reqs if status[r["id"]] != 0]
+    return {"unstable": len(bad), "unstable_nu_above_quarter": sum(1 for r in bad if r["nu"] > 0.25),
+            "unstable_nu_within_quarter": sum(1 for r in bad if r["nu"] <= 0.25),
+            "requests_nu_above_quarter": sum(1 for r in reqs if r["nu"] > 0.25)}
 
 
 def run_open(reqs, rate, seed=1, precision="f32", **server_kw):
@@ -119,11 +137,13 @@ def run_open(reqs, rate, seed=1, precision="f32", **server_kw):
             "p99_s": float(np.percentile(lat, 99)) if lat.size else None}
 
 
-def run_sequential(reqs, precision="f64"):
-    """One simulation at a time with the plain single-lattice path."""
+def run_sequential(reqs, precision="f64", check_every=500):
+    """One simulation at a time with the plain single-lattice path, checked for
+    values that are not finite every check_every steps (as the server scans
+    after each round), so that a diverging run stops early there too."""
     import torch
     from . import mclbm
-    out = {}
+    out, status, ran = {}, {}, 0.0
     t0 = time.perf_counter()
     for r in reqs:
         s = mclbm.Sim(r["nx"], r["ny"], mu=r["mu"], nu=r["nu"], tau=r["tau"], material=r["material"],
@@ -132,47 +152,79 @@ def run_sequential(reqs, precision="f64"):
             args = (spec,) if isinstance(spec, str) else tuple(spec)
             s.set_side(name, *args)
         s.init()
-        s.step(r["nsteps"])
+        ok, n = s.step_checked(r["nsteps"], every=check_every)
+        ran += r["nx"] * r["ny"] * n
+        status[r["id"]] = 0 if ok else mclbm.MCLBM_EUNSTABLE
         out[r["id"]] = s.read("u")
         del s
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     torch.cuda.empty_cache()
-    return lups(reqs) / dt, dt, out
+    stable = sum(r["nx"] * r["ny"] * r["nsteps"] for r in reqs if status[r["id"]] == 0)
+    return {"lups_per_s": ran / dt, "completed_lups_per_s": stable / dt, "requests": len(reqs), "seconds": dt,
+            **unstable_counts(reqs, status)}, out, status
+
+
+def stratified(reqs, k):
+    """k requests spread evenly over the stream's range of work (updates per
+    request), the middle of each of k equal-count bins."""
+    order = sorted(reqs, key=lambda r: r["nx"] * r["ny"] * r["nsteps"])
+    k = min(k, len(order))
+    return [order[int((i + 0.5) * len(order) / k)] for i in range(k)]
+
+
+def _phase(name, t0):
+    print(f"[serve] {name} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 
 
 def serving_report(n=1000, seed=0, steps=(1000, 20000), load=0.8, baseline=40, **server_kw):
+    t0 = time.perf_counter()
     reqs = make_requests(n, seed=seed, steps=steps)
-    cap, cap_s, res = run_closed(reqs, **server_kw)
+    f32, res = run_closed(reqs, **server_kw)
+    _phase("batched FP32", t0)
     # Poisson arrivals at `load` times the closed loop's request rate
-    opn = run_open(reqs, rate=load * len(reqs) / cap_s, **server_kw)
-    # the same stream with 16-bit population storage
-    cap16, cap16_s, res16 = run_closed(reqs, precision="f16", **server_kw)
-    sub = reqs[:baseline]
-    seq, seq_s, useq = run_sequential(sub, "f64")
+    opn = run_open(reqs, rate=load * len(reqs) / f32["closed_loop_seconds"], **server_kw)
+    _phase("open loop FP32", t0)
+    # the same stream batched with FP64 (the batching gain alone) and 16-bit storage
+    f64, res64 = run_closed(reqs, precision="f64", **server_kw)
+    _phase("batched FP64", t0)
+    f16, res16 = run_closed(reqs, precision="f16", **server_kw)
+    _phase("batched FP16", t0)
+    # one-at-a-time plain FP64 on a sample spread over the stream's sizes and lengths
+    sub = stratified(reqs, baseline)
+    seq, useq, sseq = run_sequential(sub, "f64")
+    _phase("one-at-a-time FP64", t0)
+    sample_ids = {r["id"] for r in sub}
 
     def max_err(batched):
-        # accuracy of batched results against the one-at-a-time FP64 ones
+        # accuracy of batched results against the one-at-a-time FP64 ones, on the
+        # sample's requests that both finished stably
         errs = []
         for r in sub:
             st, status, u = batched[r["id"]]
             ref = useq[r["id"]]
-            if status == 0 and np.all(np.isfinite(ref)) and np.linalg.norm(ref) > 0:
+            if status == 0 and sseq[r["id"]] == 0 and np.linalg.norm(ref) > 0:
                 errs.append(float(np.linalg.norm(u - ref) / np.linalg.norm(ref)))
-        return max(errs) if errs else None
+        return {"max": max(errs) if errs else None, "compared": len(errs)}
 
+    agree64 = sum(1 for i in sample_ids if (res64[i][1] == 0) == (sseq[i] == 0))
     return {"workload": f"{n} requests, sides 64..1024, SVK/NH, nu 0..0.45, tension/shear/cantilever, "
                         f"{steps[0]}..{steps[1]} steps, seed {seed}",
-            "batched_f32": {"capacity_lups_per_s": cap, "closed_loop_seconds": cap_s,
-                            "requests_per_s": len(reqs) / cap_s,
-                            "unstable": int(sum(1 for v in res.values() if v[1] != 0))},
+            "batched_f32": f32,
             "open_loop_f32": opn,
-            "batched_f16": {"capacity_lups_per_s": cap16, "closed_loop_seconds": cap16_s,
-                            "unstable": int(sum(1 for v in res16.values() if v[1] != 0))},
-            "sequential_f64": {"lups_per_s": seq, "requests": len(sub), "seconds": seq_s},
-            "speedup_vs_sequential_f64": cap / seq,
-            "batched_f32_vs_sequential_f64_rel_l2_u_max": max_err(res),
-            "batched_f16_vs_sequential_f64_rel_l2_u_max": max_err(res16)}
+            "batched_f64": f64,
+            "batched_f16": f16,
+            "sequential_f64": {**seq, "sample": f"{len(sub)} requests at evenly spaced quantiles of the "
+                                                "stream's updates per request",
+                               "stable_verdict_agrees_with_batched_f64": f"{agree64} of {len(sub)}"},
+            "speedup_vs_sequential_f64": f32["capacity_lups_per_s"] / seq["lups_per_s"],
+            "speedup_completed_vs_sequential_f64": f32["completed_lups_per_s"] / seq["completed_lups_per_s"]
+            if seq["completed_lups_per_s"] > 0 else None,
+            "batching_gain_f64": f64["capacity_lups_per_s"] / seq["lups_per_s"],
+            "storage_gain_f32_over_f64_batched": f32["capacity_lups_per_s"] / f64["capacity_lups_per_s"],
+            "batched_f32_vs_sequential_f64_rel_l2_u": max_err(res),
+            "batched_f64_vs_sequential_f64_rel_l2_u": max_err(res64),
+            "batched_f16_vs_sequential_f64_rel_l2_u": max_err(res16)}
 
 
 def main():
