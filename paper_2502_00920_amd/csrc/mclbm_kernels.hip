@@ -1297,26 +1297,50 @@ __device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
     else node_update<PR, false>(a, gx, gy, Sband, sig_n, Tband);
 }
 
-// The step of one lattice: one work item per wave (the nodes on non-periodic
-// sides are left to wall_kernel, launched after it).  Two waves per SIMD, but
-// one in FP64: its loop needs about 306 registers, and at two waves (256 each)
-// the 50 spilled to scratch cost more than the halved occupancy (8192^2
-// tension: 26.9k MLUPS at two waves, 28.4k at one).
-template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(StepArgs a, int nstrip, int nchunk,
-                                                                             int chunk) {
-    __shared__ HaloOf<PR, HR> halo_lds[4];
+// LDS of a step block: the four waves' halo blocks, or a wall segment's band
+template <int PR, int HR>
+union StepLds {
+    HaloOf<PR, HR> halo[4];
+    WallBand band;
+};
+
+// The step of one lattice: one work item per wave.  FUSED (FP32 and FP64
+// only): the launch also carries the wall segments, blocks [0, nwall) (nwall a
+// multiple of 8, so the march blocks after them keep their XCD order), which
+// update the nodes on non-periodic sides; else those nodes are left to
+// wall_kernel, launched after.  Both kinds of block read only level n.  (In the
+// 16-bit formats the fused kernel spilled, inlined or not, and ran 25 %
+// slower at 8192^2 and at 2048^2.)  Two waves per SIMD, but one in FP64:
+// its loop needs about 306 registers, and at two waves (256 each) the 50
+// spilled to scratch cost more than the halved occupancy (8192^2 tension:
+// 26.9k MLUPS at two waves, 28.4k at one).
+template <int PR, int MAT, int HR, int D, bool FUSED>
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(StepArgs a, int nwall, int nstrip,
+                                                                             int nchunk, int chunk) {
+    using Lds = typename std::conditional<FUSED, StepLds<PR, HR>, HaloOf<PR, HR>[4]>::type;
+    __shared__ Lds lds;
+    if constexpr (FUSED) {
+        if ((int)blockIdx.x < nwall) {
+            if ((int)blockIdx.x < wall_segs(a.g).total) {
+                const StepArgs la = a;  // a local copy: the argument block itself stays unaddressed
+                wall_segment<PR, MAT>(la, blockIdx.x, lds.band);
+            }
+            return;
+        }
+    }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
+    const int b = (int)blockIdx.x - nwall;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(b, (int)gridDim.x - nwall) * 4 + wv);
     if (item >= nstrip * nchunk) return;
-    march_item<PR, MAT, HR, D>(a, halo_lds[wv], lane, item % nstrip, item / nstrip, chunk);
+    if constexpr (FUSED) march_item<PR, MAT, HR, D>(a, lds.halo[wv], lane, item % nstrip, item / nstrip, chunk);
+    else march_item<PR, MAT, HR, D>(a, lds[wv], lane, item % nstrip, item / nstrip, chunk);
 }
 
 // The wall segments of one lattice, one block each, after march_kernel on the
-// same stream.  (Fused into march_kernel's launch, the wall blocks held their
-// slots at the start of the march: 8192^2 tension ran the same in FP32 and 2 %
-// slower in FP16.)
+// same stream (for lattices whose march fills the GPU many times over: fused
+// into the march's launch there, the wall blocks held their slots at the start
+// of the march, and 8192^2 tension ran the same in FP32 and 2 % slower in FP16).
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
     __shared__ WallBand band;
@@ -1464,13 +1488,40 @@ static int march_chunk(const Geometry& g, int nstrip, int L, long target) {
 }
 
 template <int PR, int MAT, int HR, int D>
-static void launch_march(const StepArgs& a, hipStream_t st) {
+static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);
     const int nstrip = a.g.pitch / 64;
     const int chunk = march_chunk(a.g, nstrip, L, march_waves<PR>());
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
-    hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D>), dim3((nstrip * nchunk + 3) / 4), dim3(256), 0, st, a,
-                       nstrip, nchunk, chunk);
+    const int blocks = (nstrip * nchunk + 3) / 4;
+    if constexpr (PR == PREC_F32 || PR == PREC_F64) {
+        if (fused) {
+            const int nwall = (wall_segs(a.g).total + 7) / 8 * 8;
+            hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, true>), dim3(nwall + blocks), dim3(256), 0, st, a,
+                               nwall, nstrip, nchunk, chunk);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, false>), dim3(blocks), dim3(256), 0, st, a, 0, nstrip,
+                       nchunk, chunk);
+}
+
+// Whether one lattice's step runs as one fused launch (march and wall blocks)
+// rather than march_kernel followed by wall_kernel.  Measured, back-to-back
+// steps, fused against two launches: FP32 gains at every size (tension32 and
+// shear128 1.8-1.9x, 2048 x 128 +49 %, 1024^2 +19 %, 2048^2 +5 %, 4096^2
+// +3 %, 8192^2 +0.7 %); FP64 gains while its march takes few blocks (1024^2,
+// 1024 blocks: +10 %) and loses 1-1.5 % from 2048^2 (4096 blocks) up; the
+// 16-bit formats lose everywhere.
+constexpr long kFuseBlocksF64 = 2048;
+bool step_fused(int prec, const Geometry& g) {
+    if (wall_segs(g).total == 0) return false;
+    if (prec == PREC_F32) return true;
+    if (prec != PREC_F64) return false;
+    const int nstrip = g.pitch / 64;
+    const int chunk = march_chunk(g, nstrip, 6, march_waves<PREC_F64>());
+    const long blocks = ((long)nstrip * ((g.ny + chunk - 1) / chunk) + 3) / 4;
+    return blocks <= kFuseBlocksF64;
 }
 
 template <int PR, int MAT>
@@ -1534,24 +1585,24 @@ hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int 
 }
 
 template <int PR>
-static hipError_t step_p(int material, const StepArgs& a, hipStream_t st) {
+static hipError_t step_p(int material, const StepArgs& a, bool fused, hipStream_t st) {
     // halo blocks of 6 rows, loads of 2 rows in flight: the fastest of the
     // shapes measured on the 8192^2 workload (halo blocks of 2 to 6 rows, 2 or 3
     // rows in flight), in FP32 and FP64
     switch (material) {
-    case MAT_SVK: launch_march<PR, MAT_SVK, 6, 2>(a, st); break;
-    case MAT_NH: launch_march<PR, MAT_NH, 6, 2>(a, st); break;
-    default: launch_march<PR, MAT_LIN, 6, 2>(a, st); break;
+    case MAT_SVK: launch_march<PR, MAT_SVK, 6, 2>(a, fused, st); break;
+    case MAT_NH: launch_march<PR, MAT_NH, 6, 2>(a, fused, st); break;
+    default: launch_march<PR, MAT_LIN, 6, 2>(a, fused, st); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_step(int prec, int material, const StepArgs& a, hipStream_t st) {
+hipError_t launch_step(int prec, int material, const StepArgs& a, bool fused, hipStream_t st) {
     switch (prec) {
-    case PREC_F64: return step_p<PREC_F64>(material, a, st);
-    case PREC_F32: return step_p<PREC_F32>(material, a, st);
-    case PREC_F16: return step_p<PREC_F16>(material, a, st);
-    default: return step_p<PREC_BF16>(material, a, st);
+    case PREC_F64: return step_p<PREC_F64>(material, a, fused, st);
+    case PREC_F32: return step_p<PREC_F32>(material, a, fused, st);
+    case PREC_F16: return step_p<PREC_F16>(material, a, fused, st);
+    default: return step_p<PREC_BF16>(material, a, fused, st);
     }
 }
 
