@@ -463,7 +463,7 @@ def main():
         "config": {"workload": f"tension{args.n}: St. Venant-Kirchhoff uniaxial tension, D2Q9 "
                                f"{args.n}x{args.n}, mu=0.05, nu=0.3, tau=0.55, left held, right "
                                "pulled 3.2e-3 dx/step, top/bottom traction-free",
-                   "storage": "populations " + head + ", displacement f64"},
+                   "storage": "populations " + head + "; displacement, moments, collision and wall rules f64"},
         "hbm_gbs": r["step_gbs"],
         "roofline": r["roofline"],
         "kernels": r["kernels"],
