@@ -242,7 +242,13 @@ int mclbm_set_side(mclbm_sim* s, int side, const mclbm_side_spec* spec);
  * (on_device = 1); NULL means zero.  Resets the step counter to 0. */
 int mclbm_init(mclbm_sim* s, const double* u0, const double* j0, int on_device);
 
-/* Advance nsteps >= 0 time steps, enqueued asynchronously on the stream. */
+/* Advance nsteps >= 0 time steps, enqueued asynchronously on the stream.
+ * Capturable into a HIP graph on the simulation's stream (no allocation, no
+ * memset; diag_every = 0): the captured launches keep the arguments of the
+ * steps captured (buffers by step parity, the wall values of those steps), so
+ * a replay repeats those steps; it continues the run correctly for constant
+ * wall programs and an even number of captured steps.  The handle's step
+ * count advances at capture, not at replay. */
 int mclbm_step(mclbm_sim* s, int64_t nsteps);
 
 /* Advance nsteps (1..100000) time steps as mclbm_step does, with HIP events

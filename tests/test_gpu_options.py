@@ -358,3 +358,41 @@ def test_server_runs_the_fused_step_only(M):
         with pytest.raises(M.MclbmError) as e:
             M.mclbm_server_submit(sv._h, p, sides, None, 10, out.ctypes.data)
         assert e.value.code == M.MCLBM_EINVAL
+
+
+@pytest.mark.parametrize("precision, n", [("f32", 96), ("f64", 96), ("f16", 96), ("f64", 1600)])
+def test_captured_steps_replay(M, precision, n):
+    """mclbm_step captured into a HIP graph on the simulation's own stream.  The
+    captured launches hold the captured steps' arguments (buffers by step parity,
+    the wall values of those steps), so a graph of an even number of steps under
+    constant wall programs replays as the same steps run eagerly.  Each of five
+    replays is checked bitwise against an eager twin, with the twin's eager steps
+    and a synchronisation between replays.  The lattices cover the step as one
+    launch (FP32, FP64 on few blocks) and as the march followed by the wall
+    kernel (FP16; FP64 on 1600 x 1600, 2500 march blocks)."""
+    import torch
+    print_case(f"captured steps {precision} {n}x{n}")
+    st = torch.cuda.Stream()
+    sides = {"left": ("dirichlet",), "right": ("neumann", "const", (2e-3, -1e-3)), "bottom": "neumann",
+             "top": ("dirichlet", "const", (1e-4, 0.0))}
+    u0 = W.smooth_field(n, n, 1e-3, 5)
+    sims = []
+    for _ in range(2):
+        s = M.Sim(n, n, mu=0.05, nu=0.2, tau=0.55, material="svk", precision=precision, stream=st)
+        for side, spec in sides.items():
+            s.set_side(side, *((spec,) if isinstance(spec, str) else tuple(spec)))
+        s.init(u0)
+        sims.append(s)
+    g_sim, e_sim = sims
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=st):
+        g_sim.step(4)
+    for r in range(5):
+        g.replay()
+        e_sim.step(4)
+        torch.cuda.synchronize()
+        ug, ue = g_sim.read("u"), e_sim.read("u")
+        assert np.isfinite(ue).all() and np.abs(ue).max() > 0
+        assert np.array_equal(ug, ue), (precision, n, r, float(np.abs(ug - ue).max()))
+    del g
