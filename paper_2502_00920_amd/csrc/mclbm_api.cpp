@@ -54,7 +54,7 @@ struct Layout {
 };
 
 // bytes per node of one population buffer: nine FP64 or FP32 values, or nine
-// 16-bit values (four planes of two per 32-bit word and one 16-bit plane)
+// 16-bit values (per lattice row four rows of two per 32-bit word and one row of 16-bit values)
 size_t pop_bytes_per_node(int precision) {
     return precision == MCLBM_F64 ? 72 : (precision == MCLBM_F32 ? 36 : 18);
 }
@@ -97,14 +97,13 @@ int check_params(const mclbm_params* p) {
     if (p->nx < 3 || p->ny < 3) return fail(MCLBM_EINVAL, "nx and ny must be >= 3 (got %d x %d)", p->nx, p->ny);
     if (p->precision < MCLBM_F64 || p->precision > MCLBM_BF16)
         return fail(MCLBM_EINVAL, "unknown precision %d", p->precision);
-    // the device addresses three FP64 / FP32 planes, four planes of packed 16-bit
-    // pairs, or the two displacement planes through one 32-bit buffer range each
+    // the device addresses a displacement buffer (two FP64 values per node of the
+    // pitched lattice) through one 32-bit buffer range
     {
         const int64_t plane = (int64_t)p->ny * ((p->nx + 63) / 64 * 64);
-        const int64_t range = p->precision == MCLBM_F64 ? 24 : (p->precision == MCLBM_F32 ? 12 : 16);
-        if (plane * range >= ((int64_t)1 << 32) || plane * 2 * 8 >= ((int64_t)1 << 32))
+        if (plane * 2 * 8 >= ((int64_t)1 << 32))
             return fail(MCLBM_EINVAL, "lattice of %d x %d nodes too large for one device buffer range "
-                        "(the planes one range covers must stay below 4 GiB)", p->nx, p->ny);
+                        "(a displacement buffer must stay below 4 GiB)", p->nx, p->ny);
     }
     if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
         return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");
@@ -248,7 +247,7 @@ InitLike base_args(const mclbm_sim* s, const double* u) {
     return b;
 }
 
-// copy a compact [2][ny][nx] FP64 field into a pitched [2][ny][pitch] buffer
+// copy a compact [2][ny][nx] FP64 field into a buffer of row records, [ny][2][pitch]
 int put_field2(mclbm_sim* s, double* dst, const double* src, int on_device) {
     const size_t plane = (size_t)s->g.plane;
     if (!src) {
@@ -258,7 +257,7 @@ int put_field2(mclbm_sim* s, double* dst, const double* src, int on_device) {
     const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIP_TRY(hipMemsetAsync(dst, 0, 2 * plane * sizeof(double), s->stream));
     for (int c = 0; c < 2; c++)
-        HIP_TRY(hipMemcpy2DAsync(dst + c * plane, (size_t)s->g.pitch * sizeof(double),
+        HIP_TRY(hipMemcpy2DAsync(dst + (size_t)c * s->g.pitch, 2 * (size_t)s->g.pitch * sizeof(double),
                                  src + (size_t)c * s->g.nx * s->g.ny, (size_t)s->g.nx * sizeof(double),
                                  (size_t)s->g.nx * sizeof(double), (size_t)s->g.ny, kind, s->stream));
     return MCLBM_OK;
@@ -592,7 +591,6 @@ void batch_entry(const mclbm_sim* s, int64_t k, BatchEntry* e) {
 void scan_entry(const mclbm_sim* s, int64_t k, int slot, ScanEntry* e) {
     const int c = (s->cur + (int)(k & 1)) & 1;
     e->u = static_cast<const double*>(at(s, s->L.off_u[c]));
-    e->plane = s->g.plane;
     e->limit2 = s->p.growth_limit * s->p.growth_limit;
     e->nx = s->g.nx;
     e->ny = s->g.ny;
@@ -721,13 +719,14 @@ namespace {
 // checkpoint header: 64 bytes ahead of the state
 struct CkptHeader {
     char magic[8];      // "MCLBMCK1"
-    int32_t version;    // 1
+    int32_t version;    // 2: the state in row records
     int32_t nx, ny, precision, material, time_levels;
     int64_t step;
     uint64_t f_bytes, u_bytes, extra_bytes;  // populations, displacement, held level n - 1
 };
 static_assert(sizeof(CkptHeader) == 64, "checkpoint header layout");
 constexpr char kMagic[8] = {'M', 'C', 'L', 'B', 'M', 'C', 'K', '1'};
+constexpr int32_t kVersion = 2;
 
 size_t extra_bytes(const mclbm_sim* s) { return s->L.listing ? s->L.t_bytes + s->L.s_bytes : 0; }
 
@@ -735,7 +734,7 @@ CkptHeader header_of(const mclbm_sim* s) {
     CkptHeader h;
     std::memset(&h, 0, sizeof h);
     std::memcpy(h.magic, kMagic, sizeof kMagic);
-    h.version = 1;
+    h.version = kVersion;
     h.nx = s->p.nx;
     h.ny = s->p.ny;
     h.precision = s->p.precision;
@@ -788,7 +787,7 @@ MCLBM_EXPORT int mclbm_load(mclbm_sim* s, const void* src, size_t src_bytes, int
     if (on_device) HIP_TRY(hipMemcpy(&h, d, sizeof h, hipMemcpyDeviceToHost));
     else std::memcpy(&h, d, sizeof h);
     const CkptHeader want = header_of(s);
-    if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.version != 1)
+    if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.version != kVersion)
         return fail(MCLBM_EINVAL, "not an mclbm checkpoint (magic or version)");
     if (h.nx != want.nx || h.ny != want.ny || h.precision != want.precision || h.material != want.material ||
         h.time_levels != want.time_levels || h.f_bytes != want.f_bytes || h.u_bytes != want.u_bytes ||

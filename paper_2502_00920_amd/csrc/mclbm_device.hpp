@@ -23,8 +23,23 @@ struct Geometry {
     int nx, ny;        // nodes
     int pitch;         // row pitch in elements (multiple of 64)
     int px, py;        // periodic in x / y
-    long long plane;   // elements per component plane: ny rows of pitch
+    long long plane;   // elements per component: ny rows of pitch
 };
+
+// The state (u and the populations) is stored in row records: lattice row y
+// keeps the rows of all its components side by side, [ny][component][pitch],
+// so that a wave's loads and stores of one lattice row fall in one stretch of
+// memory.  (On the 8192^2 lattice the step's access pattern alone ran 8-16 %
+// faster so than with one plane per component, [component][ny][pitch].)
+//   u (and the j0 of init): [ny][2][pitch] doubles;
+//   populations, FP64 / FP32: [ny][9][pitch];
+//   16-bit: per lattice row four rows of pitch 32-bit words (word w holds
+//   population 2w in its low half, 2w + 1 in its high half), then one row of
+//   pitch 16-bit values (population 8): 18 pitch bytes.
+// Element index of component c of node (x, y) in a [ny][2][pitch] field:
+__host__ __device__ __forceinline__ size_t u_at(const Geometry& g, int c, int y, int x) {
+    return ((size_t)y * 2 + c) * (size_t)g.pitch + x;
+}
 
 struct Coef {
     double omega;     // dt / tau, tau in units of dt

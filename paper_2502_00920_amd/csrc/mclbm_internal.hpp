@@ -6,13 +6,14 @@
 
 namespace mclbm {
 
-// Populations: [9][ny][pitch] of double or float, or for 16-bit storage four
-// planes of 32-bit words (word w: population 2w in the low half, 2w + 1 in the
-// high half) followed by one plane of population 8 (16-bit values).
+// The state in row records (u_at): populations [ny][9][pitch] of double or
+// float, or for 16-bit storage per lattice row four rows of 32-bit words (word
+// w: population 2w in the low half, 2w + 1 in the high half) and one row of
+// population 8 (16-bit values); u [ny][2][pitch] of double.
 struct StepArgs {
     const void* fsrc;  // fc'_n
     void* fdst;        // fc'_{n+1}
-    const double* usrc;  // u_n, [2][ny][pitch]
+    const double* usrc;  // u_n, [ny][2][pitch]
     double* udst;        // u_{n+1}
     Geometry g;
     Coef k;
@@ -22,7 +23,7 @@ struct StepArgs {
 // What the per-node helpers need: the displacement field and the constants of
 // the stress and source evaluation.
 struct InitLike {
-    const double* u;   // [2][ny][pitch]
+    const double* u;   // [ny][2][pitch]
     Geometry g;
     double inv_dx, inv_c2, sig_b[2], lam, mu, rho0;
     int bo;            // one-sided differences at the outermost nodes: 1 or 2
@@ -31,7 +32,7 @@ struct InitLike {
 struct InitArgs {
     InitLike b;
     void* f;           // fc'_0 out
-    const double* j0;  // [2][ny][pitch]
+    const double* j0;  // [ny][2][pitch]
     double rho0, inv_c;
     double fscale;     // stored = population * fscale
 };
@@ -100,12 +101,11 @@ inline size_t batch_step_bytes(int max_sims) {
     return (sizeof(BatchStep) + (size_t)(max_sims - 1) * sizeof(BatchEntry) + 255) / 256 * 256;
 }
 
-// One lattice's displacement for the failure scan: u at [2][ny][pitch]; the
+// One lattice's displacement for the failure scan: u at [ny][2][pitch]; the
 // scan raises flags[slot] if any u of a node is not finite or, when limit2 > 0,
 // if |u|^2 exceeds limit2.
 struct ScanEntry {
     const double* u;
-    long long plane;
     double limit2;
     int nx, ny, pitch, slot;
 };

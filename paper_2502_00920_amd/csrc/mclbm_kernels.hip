@@ -43,8 +43,9 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 __device__ __forceinline__ int wrap1(int g, int n) { return g < 0 ? g + n : (g >= n ? g - n : g); }
 
 // Raw buffer access: a wave-uniform resource (base, size in bytes), a
-// wave-uniform SGPR offset and a 32-bit byte offset per lane.  Three component
-// planes share one resource, so that a step needs eight resources in all.
+// wave-uniform SGPR offset and a 32-bit byte offset per lane.  The march takes
+// one resource per displacement buffer and, for the populations, one per lattice
+// row (its record), so that no 32-bit range limits the population buffers.
 constexpr uint32_t kRsrcWord3 = 0x00020000;  // gfx9-family buffer format word
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
@@ -76,10 +77,10 @@ __device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, uint32_t ob,
 
 // ---- population storage formats ----------------------------------------------------------
 //
-// FP64 and FP32: nine planes of double / float.  FP16 and BF16: the populations two
-// per 32-bit word in four planes (word w holds population 2w in its low half and
-// 2w + 1 in its high half) and population 8 in a fifth plane of 16-bit values, 18
-// bytes per node.  In this scheme the rest state has f = 0, so the stored values
+// FP64 and FP32: nine rows of double / float per lattice row.  FP16 and BF16: the
+// populations two per 32-bit word in four rows (word w holds population 2w in its
+// low half and 2w + 1 in its high half) and population 8 in a fifth row of 16-bit
+// values, 18 bytes per node.  In this scheme the rest state has f = 0, so the stored values
 // are the deviation from that equilibrium.  FP16 values are the populations times a
 // power of two (Coef::fscale) that keeps them out of the subnormal range; BF16 has
 // FP32's exponent range and is stored unscaled.  Arithmetic is FP32 for all three.
@@ -96,7 +97,7 @@ __device__ __forceinline__ uint32_t bf16_bits(float v) {
 __device__ __forceinline__ float bf16_value(uint32_t b) { return __builtin_bit_cast(float, (b & 0xffffu) << 16); }
 
 template <int PR>
-struct Store {  // PREC_F64, PREC_F32: plain planes
+struct Store {  // PREC_F64, PREC_F32: plain values
     using T = typename std::conditional<PR == PREC_F64, double, float>::type;  // arithmetic
     using TS = T;  // stresses, source and their halo
     using ST = T;  // storage
@@ -121,30 +122,38 @@ struct Store<PREC_BF16> {
     __device__ static float dec(uint32_t b) { return bf16_value(b); }
 };
 
-// population q of the node at element offset o, for the per-node kernels
+// bytes of one lattice row's record of populations (see u_at for the layout)
 template <int PR>
-__device__ __forceinline__ double pop_get(const void* f, size_t plane, size_t o, int q, double finv) {
+__host__ __device__ constexpr uint32_t pop_row_bytes(int pitch) {
+    return (uint32_t)pitch * (PR == PREC_F64 ? 72u : (PR == PREC_F32 ? 36u : 18u));
+}
+
+// population q of node (x, y), for the per-node kernels
+template <int PR>
+__device__ __forceinline__ double pop_get(const void* f, const Geometry& g, int y, int x, int q, double finv) {
     using S = Store<PR>;
     if constexpr (!S::packed) {
-        return (double)reinterpret_cast<const typename S::ST*>(f)[(size_t)q * plane + o];
+        return (double)reinterpret_cast<const typename S::ST*>(f)[((size_t)y * 9 + q) * g.pitch + x];
     } else {
-        const uint32_t* w = reinterpret_cast<const uint32_t*>(f);
-        if (q == 8) return (double)S::dec(reinterpret_cast<const uint16_t*>(w + 4 * plane)[o]) * finv;
-        const uint32_t v = w[(size_t)(q >> 1) * plane + o];
+        const size_t row = (size_t)y * 9 * g.pitch;  // the record's first 16-bit unit
+        if (q == 8) return (double)S::dec(reinterpret_cast<const uint16_t*>(f)[row + 8 * (size_t)g.pitch + x]) * finv;
+        const uint32_t v = reinterpret_cast<const uint32_t*>(f)[row / 2 + (size_t)(q >> 1) * g.pitch + x];
         return (double)S::dec((q & 1) ? (v >> 16) : v) * finv;
     }
 }
 template <int PR>
-__device__ __forceinline__ void pop_put_all(void* f, size_t plane, size_t o, const double v[9], double fscale) {
+__device__ __forceinline__ void pop_put_all(void* f, const Geometry& g, int y, int x, const double v[9], double fscale) {
     using S = Store<PR>;
     if constexpr (!S::packed) {
-        for (int q = 0; q < 9; q++) reinterpret_cast<typename S::ST*>(f)[(size_t)q * plane + o] = (typename S::ST)v[q];
+        for (int q = 0; q < 9; q++)
+            reinterpret_cast<typename S::ST*>(f)[((size_t)y * 9 + q) * g.pitch + x] = (typename S::ST)v[q];
     } else {
+        const size_t row = (size_t)y * 9 * g.pitch;
         uint32_t* w = reinterpret_cast<uint32_t*>(f);
         for (int k = 0; k < 4; k++)
-            w[(size_t)k * plane + o] =
+            w[row / 2 + (size_t)k * g.pitch + x] =
                 S::enc((float)(v[2 * k] * fscale)) | (S::enc((float)(v[2 * k + 1] * fscale)) << 16);
-        reinterpret_cast<uint16_t*>(w + 4 * plane)[o] = (uint16_t)S::enc((float)(v[8] * fscale));
+        reinterpret_cast<uint16_t*>(f)[row + 8 * (size_t)g.pitch + x] = (uint16_t)S::enc((float)(v[8] * fscale));
     }
 }
 
@@ -340,20 +349,20 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
     const bool inner_y = g.py ? (yc - 5 >= 0 && rmax <= g.ny - 1) : (yc - 5 >= 1 && rmax <= g.ny - 2);
     const bool inner_x = g.px ? (x0 >= 3 && x0 + 66 <= g.nx - 1) : (x0 >= 4 && x0 + 66 <= g.nx - 2);
 
-    const size_t plane = (size_t)g.plane;
-    const uint32_t pbD = (uint32_t)(plane * sizeof(double));
-    // bytes per plane: of T (three planes per resource), or of 32-bit words (four
-    // planes in one resource, the 16-bit plane in another)
-    const uint32_t pbT = (uint32_t)(plane * (PK ? 4 : sizeof(ST)));
+    // row records (u_at): u through one resource per buffer, its component rows
+    // pbU bytes apart; the populations through a resource per lattice row, their
+    // component rows pbF bytes apart (32-bit words: the 16-bit row at 4 pbF)
+    const uint32_t pbU = (uint32_t)g.pitch * (uint32_t)sizeof(double);
+    const uint32_t pbF = (uint32_t)g.pitch * (uint32_t)(PK ? 4 : sizeof(ST));
+    const uint32_t recF = pop_row_bytes<PR>(g.pitch);
     const char* fs = reinterpret_cast<const char*>(a.fsrc);
     char* fd = reinterpret_cast<char*>(a.fdst);
-    const __amdgpu_buffer_rsrc_t rs0 = rsrc(fs, (PK ? 4 : 3) * pbT),
-                                 rs1 = rsrc(fs + (PK ? 4 : 3) * (size_t)pbT, PK ? pbT / 2 : 3 * pbT),
-                                 rs2 = rsrc(fs + 6 * (size_t)pbT, PK ? 0 : 3 * pbT);
-    const __amdgpu_buffer_rsrc_t rd0 = rsrc(fd, (PK ? 4 : 3) * pbT),
-                                 rd1 = rsrc(fd + (PK ? 4 : 3) * (size_t)pbT, PK ? pbT / 2 : 3 * pbT),
-                                 rd2 = rsrc(fd + 6 * (size_t)pbT, PK ? 0 : 3 * pbT);
-    const __amdgpu_buffer_rsrc_t rus = rsrc(a.usrc, 2 * pbD), rud = rsrc(a.udst, 2 * pbD);
+    const uint32_t ubytes = (uint32_t)((size_t)g.plane * 2 * sizeof(double));
+    const __amdgpu_buffer_rsrc_t rus = rsrc(a.usrc, ubytes), rud = rsrc(a.udst, ubytes);
+    // the record of lattice row y (wave-uniform) of a population buffer
+    auto frow = [&](const char* base, int y) {
+        return rsrc(base + (size_t)__builtin_amdgcn_readfirstlane(y) * recF, recF);
+    };
     const T finv = T(a.k.finv), fscl = T(a.k.fscale);
     const double idx = a.k.inv_dx;
     const TS ic2 = TS(a.k.inv_c2), sbx = TS(a.k.sig_b[0]), sby = TS(a.k.sig_b[1]);
@@ -382,24 +391,23 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         auto hi_row = [&](int r) { return EDGE && !g.py && r >= g.ny - 1; };
 
         auto load_u = [&](int r, double v[2]) {
-            const uint32_t ob = (uint32_t)(rowp(r) * g.pitch + x) * (uint32_t)sizeof(double);
+            const uint32_t ob = (uint32_t)(rowp(r) * 2 * g.pitch + x) * (uint32_t)sizeof(double);
             v[0] = bload(rus, ob, 0u, 0.0);
-            v[1] = bload(rus, ob, pbD, 0.0);
+            v[1] = bload(rus, ob, pbU, 0.0);
         };
         // a row of populations as loaded (decoded only when consumed, so that the
         // loads stay in flight)
         auto load_f = [&](int r, Raw f[NRAW]) {
-            const uint32_t o = (uint32_t)(rowp(r) * g.pitch + x);
+            const __amdgpu_buffer_rsrc_t rs = frow(fs, rowp(r));
             if constexpr (PK) {
 #pragma unroll
                 for (int w = 0; w < 4; w++)
-                    f[w] = __builtin_amdgcn_raw_buffer_load_b32(rs0, o * 4u, (uint32_t)w * pbT, 0);
-                f[4] = __builtin_amdgcn_raw_buffer_load_b16(rs1, o * 2u, 0u, 0);
+                    f[w] = __builtin_amdgcn_raw_buffer_load_b32(rs, (uint32_t)x * 4u, (uint32_t)w * pbF, 0);
+                f[4] = __builtin_amdgcn_raw_buffer_load_b16(rs, (uint32_t)x * 2u, 4u * pbF, 0);
             } else {
-                const uint32_t ob = o * (uint32_t)sizeof(ST);
+                const uint32_t ob = (uint32_t)x * (uint32_t)sizeof(ST);
 #pragma unroll
-                for (int q = 0; q < 9; q++)
-                    f[q] = bload(q < 3 ? rs0 : (q < 6 ? rs1 : rs2), ob, (uint32_t)(q % 3) * pbT, ST(0));
+                for (int q = 0; q < 9; q++) f[q] = bload(rs, ob, (uint32_t)q * pbF, ST(0));
             }
         };
         auto decode = [&](const Raw f[NRAW], T F[9]) {
@@ -415,23 +423,24 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
                 for (int q = 0; q < 9; q++) F[q] = T(f[q]);
             }
         };
-        auto store_node = [&](uint32_t node, double ux, double uy, const T fn[9]) {
-            const uint32_t ou = node * (uint32_t)sizeof(double);
+        // the new state of this lane's node (column vx) of row r (wave-uniform)
+        auto store_node = [&](int r, double ux, double uy, const T fn[9]) {
+            const uint32_t ou = (uint32_t)(r * 2 * g.pitch + vx) * (uint32_t)sizeof(double);
             bstore_nt(rud, ou, 0u, ux);
-            bstore_nt(rud, ou, pbD, uy);
+            bstore_nt(rud, ou, pbU, uy);
+            const __amdgpu_buffer_rsrc_t rd = frow(fd, r);
             if constexpr (PK) {
 #pragma unroll
                 for (int w = 0; w < 4; w++)
                     __builtin_amdgcn_raw_buffer_store_b32(
-                        SF::enc(fn[2 * w] * fscl) | (SF::enc(fn[2 * w + 1] * fscl) << 16), rd0, node * 4u,
-                        (uint32_t)w * pbT, kCpolNT);
-                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)SF::enc(fn[8] * fscl), rd1, node * 2u, 0u,
-                                                      kCpolNT);
+                        SF::enc(fn[2 * w] * fscl) | (SF::enc(fn[2 * w + 1] * fscl) << 16), rd, (uint32_t)vx * 4u,
+                        (uint32_t)w * pbF, kCpolNT);
+                __builtin_amdgcn_raw_buffer_store_b16((unsigned short)SF::enc(fn[8] * fscl), rd, (uint32_t)vx * 2u,
+                                                      4u * pbF, kCpolNT);
             } else {
-                const uint32_t of = node * (uint32_t)sizeof(ST);
+                const uint32_t of = (uint32_t)vx * (uint32_t)sizeof(ST);
 #pragma unroll
-                for (int q = 0; q < 9; q++)
-                    bstore_nt(q < 3 ? rd0 : (q < 6 ? rd1 : rd2), of, (uint32_t)(q % 3) * pbT, ST(fn[q]));
+                for (int q = 0; q < 9; q++) bstore_nt(rd, of, (uint32_t)q * pbF, ST(fn[q]));
             }
         };
 
@@ -497,7 +506,8 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
         // lane j < 6 HR: the halo population of side j / (3 HR), pull (j / HR) % 3, row j % HR
         auto hrow = [](int pi) { return pi == 0 ? 3 : (pi == 1 ? 2 : 4); };  // its block row k - rel
         // where this lane's halo population sits in a packed word: the high half?
-        // (population 8: the parity of its column, as the row pitch is even)
+        // (population 8: the parity of its column, as every row of a record starts
+        // at an even 16-bit unit)
         const bool ghigh = [&] {
             const int j = min(lane, 6 * HR - 1);
             const int sd = j / (3 * HR);
@@ -513,21 +523,22 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
 #pragma unroll
             for (int sd = 0; sd < 2; sd++) {
                 const int hx = colp(sd == 0 ? x0 - 3 + c : x0 + 62 + c);
-                const uint32_t ob = (uint32_t)(rr * g.pitch + hx) * (uint32_t)sizeof(double);
+                const uint32_t ob = (uint32_t)(rr * 2 * g.pitch + hx) * (uint32_t)sizeof(double);
                 gu[sd][0] = bload(rus, ob, 0u, 0.0);
-                gu[sd][1] = bload(rus, ob, pbD, 0.0);
+                gu[sd][1] = bload(rus, ob, pbU, 0.0);
             }
             const int j = min(lane, 6 * HR - 1);
             const int sd = j / (3 * HR), pi = (j % (3 * HR)) / HR, k2 = j % HR + hrow(pi);
             const int hx = colp(sd == 0 ? x0 - 1 : x0 + 64);
             const int p = halo_pop(sd, pi);
-            const size_t o = (size_t)rowp(r0 - 3 + k2) * g.pitch + hx;
+            const size_t gy = (size_t)rowp(r0 - 3 + k2);
             if constexpr (PK) {
-                // population 8 from the 32-bit word of its 16-bit plane that holds it
+                // population 8 from the 32-bit word of its 16-bit row that holds it
                 const uint32_t* w = reinterpret_cast<const uint32_t*>(fs);
-                gf = p == 8 ? w[4 * plane + (o >> 1)] : w[(size_t)(p >> 1) * plane + o];
+                const size_t row = gy * 9 * (size_t)g.pitch;  // the record's first 16-bit unit
+                gf = p == 8 ? w[(row + 8 * (size_t)g.pitch + hx) >> 1] : w[row / 2 + (size_t)(p >> 1) * g.pitch + hx];
             } else {
-                gf = reinterpret_cast<const ST*>(fs)[(size_t)p * plane + o];
+                gf = reinterpret_cast<const ST*>(fs)[(gy * 9 + p) * g.pitch + hx];
             }
         };
         auto halo = [&](int r0, bool full) {
@@ -706,7 +717,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
             // launch write those nodes (rows wave-uniform; lanes only in the
             // edge copy of the loop)
             if (r >= yc && r < ye && !lo_row(r) && !hi_row(r) && !atL && !atR)
-                store_node((uint32_t)(r * g.pitch + vx), U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
+                store_node(r, U0[0] + a.k.ucoef * (m1x + o1x + (double)G0[0]),
                            U0[1] + a.k.ucoef * (m1y + o1y + (double)G0[1]), fn);
 
             U0[0] = U1[0]; U0[1] = U1[1];
@@ -772,7 +783,7 @@ __device__ __forceinline__ void march_item(const StepArgs& a, HaloOf<PR, HR>& hl
 // ---- per-node helpers for init, read-out, diagnostics and the multi-pass step (FP64) -------
 
 __device__ __forceinline__ double ld_u(const InitLike& a, int c, int gx, int gy) {
-    return a.u[(size_t)c * a.g.plane + (size_t)gy * a.g.pitch + gx];
+    return a.u[u_at(a.g, c, gy, gx)];
 }
 
 // Difference of a field along one axis at index m (0..n-1) of that axis, times
@@ -837,8 +848,6 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (gx >= a.b.g.nx || gy >= a.b.g.ny) return;
-    const size_t plane = (size_t)a.b.g.plane;
-    const size_t o = (size_t)gy * a.b.g.pitch + gx;
     double H[4];
     node_H(a.b, gx, gy, H);
     const double tr = H[0] + H[3];
@@ -847,11 +856,11 @@ __global__ __launch_bounds__(256) void init_kernel(InitArgs a) {
     const double m2xx = -a.b.mu * (H[0] + H[0] + tr) * ic2;
     const double m2xy = -a.b.mu * (H[1] + H[2]) * ic2;
     const double m2yy = -a.b.mu * (H[3] + H[3] + tr) * ic2;
-    const double m1x = a.j0[o] * a.inv_c, m1y = a.j0[plane + o] * a.inv_c;
+    const double m1x = a.j0[u_at(a.b.g, 0, gy, gx)] * a.inv_c, m1y = a.j0[u_at(a.b.g, 1, gy, gx)] * a.inv_c;
     double v[9];
 #pragma unroll
     for (int q = 0; q < 9; q++) v[q] = feq_q<double>(q, r0, m1x, m1y, m2xx, m2xy, m2yy);
-    pop_put_all<PR>(a.f, plane, o, v, a.fscale);
+    pop_put_all<PR>(a.f, a.b.g, gy, gx, v, a.fscale);
 }
 
 // ---- read-out -----------------------------------------------------------------------------
@@ -874,8 +883,6 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
     const Geometry& g = a.b.g;
     if (gx >= g.nx || gy >= g.ny) return;
-    const size_t plane = (size_t)g.plane;
-    const size_t o = (size_t)gy * g.pitch + gx;
     const size_t oc = (size_t)gy * g.nx + gx, pc = (size_t)g.nx * g.ny;  // compact output
     double* d = a.dst;
     // component c of the field goes to plane c - c0 when c0 <= c < c1
@@ -884,14 +891,14 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     };
     switch (a.field) {
     case 0:  // U
-        put(0, a.b.u[o]);
-        put(1, a.b.u[plane + o]);
+        put(0, a.b.u[u_at(g, 0, gy, gx)]);
+        put(1, a.b.u[u_at(g, 1, gy, gx)]);
         break;
     case 1: {  // J = c (M1' + sigma / 2)
         double s[2], mx = 0, my = 0;
         collision_sigma<MAT>(a, gx, gy, s);
         for (int q = 0; q < 9; q++) {
-            const double v = pop_get<PR>(a.f, plane, o, q, a.finv);
+            const double v = pop_get<PR>(a.f, g, gy, gx, q, a.finv);
             mx += ex(q) * v;
             my += ey(q) * v;
         }
@@ -903,7 +910,7 @@ __global__ __launch_bounds__(256) void read_kernel(ReadArgs a) {
     case 3: {  // PI = c^2 M2'
         double r = 0, pxx = 0, pxy = 0, pyy = 0;
         for (int q = 0; q < 9; q++) {
-            const double v = pop_get<PR>(a.f, plane, o, q, a.finv);
+            const double v = pop_get<PR>(a.f, g, gy, gx, q, a.finv);
             r += v;
             pxx += ex(q) * ex(q) * v;
             pxy += ex(q) * ey(q) * v;
@@ -955,17 +962,15 @@ __device__ __forceinline__ double wave_reduce(double v, bool take_max) {
 template <int PR, int MAT>
 __device__ __forceinline__ void diag_node(const ReadArgs& a, int gx, int gy, double v[5]) {
     const Geometry& g = a.b.g;
-    const size_t plane = (size_t)g.plane;
-    const size_t o = (size_t)gy * g.pitch + gx;
     double mx = 0, my = 0, s[2];
     for (int q = 0; q < 9; q++) {
-        const double w = pop_get<PR>(a.f, plane, o, q, a.finv);
+        const double w = pop_get<PR>(a.f, g, gy, gx, q, a.finv);
         mx += ex(q) * w;
         my += ey(q) * w;
     }
     collision_sigma<MAT>(a, gx, gy, s);
     const double jx = a.c * (mx + 0.5 * s[0]), jy = a.c * (my + 0.5 * s[1]);
-    const double ux = a.b.u[o], uy = a.b.u[plane + o];
+    const double ux = a.b.u[u_at(g, 0, gy, gx)], uy = a.b.u[u_at(g, 1, gy, gx)];
     v[0] = a.c * mx;
     v[1] = a.c * my;
     v[2] = (jx * jx + jy * jy) / (2.0 * a.b.rho0);
@@ -1110,12 +1115,10 @@ __device__ __forceinline__ InitLike init_like(const StepArgs& a, int bo) {
 template <int PR, bool TWO_RATES, typename SigC, typename SigN, typename TW>
 __device__ __forceinline__ void node_update(const StepArgs& a, int gx, int gy, SigC sig_c, SigN sig_n, TW Tw) {
     const Geometry& g = a.g;
-    const size_t plane = (size_t)g.plane;
-    const size_t o = (size_t)gy * g.pitch + gx;
     const double finv = a.k.finv;
     double fo[9], f[9];
 #pragma unroll
-    for (int q = 0; q < 9; q++) fo[q] = pop_get<PR>(a.fsrc, plane, o, q, finv);
+    for (int q = 0; q < 9; q++) fo[q] = pop_get<PR>(a.fsrc, g, gy, gx, q, finv);
     // pulls with the forcing of the collision at the source node
 #pragma unroll
     for (int q = 0; q < 9; q++) {
@@ -1126,7 +1129,7 @@ __device__ __forceinline__ void node_update(const StepArgs& a, int gx, int gy, S
         if (sx < 0 || sx >= g.nx || sy < 0 || sy >= g.ny) continue;
         double sg[2];
         sig_c(sx, sy, sg);
-        f[q] = pop_get<PR>(a.fsrc, plane, (size_t)sy * g.pitch + sx, q, finv) +
+        f[q] = pop_get<PR>(a.fsrc, g, sy, sx, q, finv) +
                3.0 * wq<double>(q) * (ex(q) * sg[0] + ey(q) * sg[1]);
     }
     const bool atL = !g.px && gx == 0, atR = !g.px && gx == g.nx - 1;
@@ -1140,18 +1143,16 @@ __device__ __forceinline__ void node_update(const StepArgs& a, int gx, int gy, S
             if (atL || atR) {  // the x wall's inward node
                 const int xi = atL ? gx + 1 : gx - 1;
                 Tw(xi, gy, txi);
-                const size_t oi = (size_t)gy * g.pitch + xi;
 #pragma unroll
                 for (int q = 2; q < 9; q++)
-                    if (ey(q) != 0) myi += pop_get<PR>(a.fsrc, plane, oi, q, finv);
+                    if (ey(q) != 0) myi += pop_get<PR>(a.fsrc, g, gy, xi, q, finv);
             }
             if (wyB || wyT) {  // the y wall's inward node
                 const int yi = wyB ? gy + 1 : gy - 1;
                 Tw(gx, yi, tyi);
-                const size_t oi = (size_t)yi * g.pitch + gx;
 #pragma unroll
                 for (int q = 1; q < 9; q++)
-                    if (ex(q) != 0) mxi += pop_get<PR>(a.fsrc, plane, oi, q, finv);
+                    if (ex(q) != 0) mxi += pop_get<PR>(a.fsrc, g, yi, gx, q, finv);
             }
         }
         apply_walls(a.w, a.k, atL, atR, wyB, wyT, fo, sc[0], sc[1], td, txi[0], txi[2], myi, tyi[1], tyi[3], mxi, f);
@@ -1167,11 +1168,12 @@ __device__ __forceinline__ void node_update(const StepArgs& a, int gx, int gy, S
     }
     double sn[2];
     sig_n(sn);
-    a.udst[o] = a.usrc[o] + a.k.ucoef * (m1x + o1x + 0.5 * (sn[0] + sc[0]));
-    a.udst[plane + o] = a.usrc[plane + o] + a.k.ucoef * (m1y + o1y + 0.5 * (sn[1] + sc[1]));
+    const size_t ox = u_at(g, 0, gy, gx), oy = u_at(g, 1, gy, gx);
+    a.udst[ox] = a.usrc[ox] + a.k.ucoef * (m1x + o1x + 0.5 * (sn[0] + sc[0]));
+    a.udst[oy] = a.usrc[oy] + a.k.ucoef * (m1y + o1y + 0.5 * (sn[1] + sc[1]));
     double fn[9];
     collide_node<TWO_RATES>(f, collide_rates(a.k.omega, a.k.omega_p), fn);
-    pop_put_all<PR>(a.fdst, plane, o, fn, a.k.fscale);
+    pop_put_all<PR>(a.fdst, g, gy, gx, fn, a.k.fscale);
 }
 
 template <int PR, bool TWO_RATES>
@@ -1447,8 +1449,8 @@ __global__ __launch_bounds__(256) void nanscan_kernel(const ScanEntry* __restric
         const uint32_t nodes = (uint32_t)s.nx * (uint32_t)s.ny, nx = (uint32_t)s.nx;
         bool bad = false;
         for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nodes; i += nthreads) {
-            const size_t o = (size_t)(i / nx) * (size_t)s.pitch + i % nx;
-            const double ux = s.u[o], uy = s.u[(size_t)s.plane + o];
+            const size_t o = (size_t)(i / nx) * 2 * (size_t)s.pitch + i % nx;  // row records
+            const double ux = s.u[o], uy = s.u[o + (size_t)s.pitch];
             bad |= !isfinite(ux) || !isfinite(uy) || (s.limit2 > 0.0 && ux * ux + uy * uy > s.limit2);
         }
         const uint64_t any = __builtin_amdgcn_ballot_w64(bad);

@@ -65,9 +65,10 @@ def test_plan_validation(M):
         assert e.value.code == M.MCLBM_EINVAL
     M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, tau_plus=0.8))  # the option is accepted
     M.mclbm_plan(M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0, growth_limit=2.5))
-    # the largest lattices: each 32-bit buffer range of planes must stay below 4 GiB
+    # the largest lattices: a displacement buffer (16 B per node of the pitched
+    # lattice) must stay below 4 GiB, whatever the population storage
     for n, prec, ok in ((16320, "f32", True), (16384, "f32", False), (16320, "bf16", True),
-                        (13376, "f64", True), (13440, "f64", False)):
+                        (16320, "f64", True), (16384, "f64", False), (16384, "f16", False)):
         p = M.make_params(n, n, mu=0.05, nu=0.3, tau=0.55, precision=prec)
         if ok:
             assert M.mclbm_plan(p)[0] > 0
@@ -254,7 +255,7 @@ def test_table_program_validation_without_gpu(M):
         M.mclbm_destroy(h)
 
 
-def _header(nx, ny, precision, material, time_levels, step, f_bytes, u_bytes, extra, magic=b"MCLBMCK1", version=1):
+def _header(nx, ny, precision, material, time_levels, step, f_bytes, u_bytes, extra, magic=b"MCLBMCK1", version=2):
     import struct
     return struct.pack("<8s6iq3Q", magic, version, nx, ny, precision, material, time_levels, step,
                        f_bytes, u_bytes, extra)
@@ -275,7 +276,7 @@ def test_checkpoint_header_is_checked_without_gpu(M):
         cases = [
             _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0)[:40],                  # short
             _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0, magic=b"NOTMCLBM"),    # foreign
-            _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0, version=2),            # format version
+            _header(16, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0, version=1),            # the planar format
             _header(17, 16, 1, 0, 0, 5, f_bytes, u_bytes, 0),                       # lattice
             _header(16, 16, 0, 0, 0, 5, 72 * plane, u_bytes, 0),                    # storage
             _header(16, 16, 1, 1, 0, 5, f_bytes, u_bytes, 0),                       # material
