@@ -3,12 +3,17 @@
 // owns 64 aligned columns of a strip and marches a chunk of rows (two priming
 // rows read, not stored), reading each node's population words and its two
 // FP64 u values and writing them to the other buffer, with two rows of loads in
-// flight, on the same block-to-XCD order as march_kernel.  Formats: FP32 (9 x
-// 32-bit planes), 16-bit (4 x 32-bit word planes + 1 x 16-bit plane, the FP16
-// and BF16 layout), FP64 (9 x 64-bit planes); chunks of 34 and 64 rows; two or
-// one waves per SIMD (set with 64 or 96 KiB of dynamic LDS per block).  Prints
-// one JSON line per case: the mean launch time over 20 launches and the rate in
-// the kernel's compulsory bytes (104, 68, 176 B per node).
+// flight, on the same block-to-XCD order as march_kernel.
+//   Formats: FP32 (nine 32-bit populations), 16-bit (four 32-bit words and one
+//   16-bit value, the FP16 and BF16 layout), FP64 (nine 64-bit populations).
+//   Layouts: row records, [ny][component][pitch] (the state's layout: one
+//   buffer resource per lattice row of populations), and planar,
+//   [component][ny][pitch] (one plane per component; three planes, or the four
+//   word planes, per resource).
+//   Chunks of 34 and 64 rows; two or one waves per SIMD (set with 64 or 96 KiB
+//   of dynamic LDS per block).
+// Prints one JSON line per case: the mean launch time over 20 launches and the
+// rate in the kernel's compulsory bytes (104, 68, 176 B per node).
 //
 // Usage: march_pattern [n]   (an n x n lattice, default 8192)
 #include <hip/hip_runtime.h>
@@ -16,7 +21,6 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
-#include <vector>
 
 #define CK(x)                                                                            \
     do {                                                                                 \
@@ -40,21 +44,28 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 struct Args {
     const char* fs;
     char* fd;
-    const double* us;
-    double* ud;
+    const char* us;
+    char* ud;
     int nx, ny, pitch, nstrip, nchunk, chunk;
     long long plane;
 };
 
+// FMT 0: FP32, 1: 16-bit, 2: FP64
+template <int FMT>
+struct Fmt {
+    static constexpr int NW = FMT == 1 ? 5 : 9;                               // words per node
+    static constexpr uint32_t node_bytes = FMT == 0 ? 36 : (FMT == 1 ? 18 : 72);
+    __host__ __device__ static constexpr uint32_t es(int w) { return FMT == 0 ? 4 : (FMT == 1 ? (w < 4 ? 4 : 2) : 8); }
+};
 template <int FMT>
 struct Row {
-    static constexpr int NW = FMT == 0 ? 9 : (FMT == 1 ? 5 : 9);
-    uint64_t w[NW];
+    uint64_t w[Fmt<FMT>::NW];
     double u[2];
 };
 
-template <int FMT>
+template <int FMT, bool RR>
 __global__ __launch_bounds__(256) void probe(Args a) {
+    using F = Fmt<FMT>;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
     if (item >= a.nstrip * a.nchunk) return;
@@ -62,68 +73,80 @@ __global__ __launch_bounds__(256) void probe(Args a) {
     const int x = strip * 64 + lane;
     const int yc = chk * a.chunk, ye = min(yc + a.chunk, a.ny);
     const int y0 = max(yc - 2, 0);
-    const uint32_t pl = (uint32_t)a.plane;
-    // resources: three planes each (FP32, FP64), or four word planes + one 16-bit plane
-    const uint32_t es = FMT == 2 ? 8u : 4u;
-    __amdgpu_buffer_rsrc_t s0, s1, s2, d0, d1, d2;
-    if (FMT == 1) {
-        s0 = rsrc(a.fs, 4 * pl * 4);
-        s1 = rsrc(a.fs + (size_t)4 * pl * 4, pl * 2);
-        s2 = s1;
-        d0 = rsrc(a.fd, 4 * pl * 4);
-        d1 = rsrc(a.fd + (size_t)4 * pl * 4, pl * 2);
-        d2 = d1;
-    } else {
-        s0 = rsrc(a.fs, 3 * pl * es);
-        s1 = rsrc(a.fs + (size_t)3 * pl * es, 3 * pl * es);
-        s2 = rsrc(a.fs + (size_t)6 * pl * es, 3 * pl * es);
-        d0 = rsrc(a.fd, 3 * pl * es);
-        d1 = rsrc(a.fd + (size_t)3 * pl * es, 3 * pl * es);
-        d2 = rsrc(a.fd + (size_t)6 * pl * es, 3 * pl * es);
-    }
-    const __amdgpu_buffer_rsrc_t us = rsrc(a.us, 2 * pl * 8), ud = rsrc(a.ud, 2 * pl * 8);
-    auto load = [&](int r, Row<FMT>& R) {
-        const uint32_t node = (uint32_t)(r * a.pitch + x);
-        if constexpr (FMT == 1) {
-#pragma unroll
-            for (int w = 0; w < 4; w++) R.w[w] = __builtin_amdgcn_raw_buffer_load_b32(s0, node * 4u, (uint32_t)w * pl * 4u, 0);
-            R.w[4] = __builtin_amdgcn_raw_buffer_load_b16(s1, node * 2u, 0u, 0);
-        } else if constexpr (FMT == 0) {
-#pragma unroll
-            for (int q = 0; q < 9; q++)
-                R.w[q] = __builtin_amdgcn_raw_buffer_load_b32(q < 3 ? s0 : (q < 6 ? s1 : s2), node * 4u,
-                                                              (uint32_t)(q % 3) * pl * 4u, 0);
+    const uint32_t P = (uint32_t)a.pitch, pl = (uint32_t)a.plane;
+    const uint32_t rec = F::node_bytes * P;  // one lattice row's record of populations
+    // planar: resources of three planes (FP32, FP64) or of the word planes and the 16-bit plane
+    __amdgpu_buffer_rsrc_t ps[3], pd[3];
+    if (!RR) {
+        if (FMT == 1) {
+            ps[0] = ps[1] = rsrc(a.fs, 16 * pl);
+            ps[2] = rsrc(a.fs + (size_t)16 * pl, 2 * pl);
+            pd[0] = pd[1] = rsrc(a.fd, 16 * pl);
+            pd[2] = rsrc(a.fd + (size_t)16 * pl, 2 * pl);
         } else {
-#pragma unroll
-            for (int q = 0; q < 9; q++)
-                R.w[q] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(
-                                                          q < 3 ? s0 : (q < 6 ? s1 : s2), node * 8u,
-                                                          (uint32_t)(q % 3) * pl * 8u, 0));
+            const uint32_t e = F::es(0);
+            for (int k = 0; k < 3; k++) {
+                ps[k] = rsrc(a.fs + (size_t)3 * k * pl * e, 3 * pl * e);
+                pd[k] = rsrc(a.fd + (size_t)3 * k * pl * e, 3 * pl * e);
+            }
         }
-        R.u[0] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(us, node * 8u, 0u, 0));
-        R.u[1] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(us, node * 8u, pl * 8u, 0));
+    }
+    const __amdgpu_buffer_rsrc_t us = rsrc(a.us, 16 * pl), ud = rsrc(a.ud, 16 * pl);
+    // word w of row r: the resource, the lane's offset and the wave's offset
+    auto where = [&](const char* base, const __amdgpu_buffer_rsrc_t* pr, int r, int w, __amdgpu_buffer_rsrc_t& rs,
+                     uint32_t& vo, uint32_t& so) {
+        if (RR) {
+            rs = rsrc(base + (size_t)r * rec, rec);
+            vo = (uint32_t)x * F::es(w);
+            so = FMT == 1 ? (uint32_t)w * 4u * P : (uint32_t)w * F::es(w) * P;
+        } else if (FMT == 1) {
+            rs = pr[w < 4 ? 0 : 2];
+            vo = (uint32_t)(r * P + x) * F::es(w);
+            so = w < 4 ? (uint32_t)w * pl * 4u : 0u;
+        } else {
+            rs = pr[w / 3];
+            vo = (uint32_t)(r * P + x) * F::es(w);
+            so = (uint32_t)(w % 3) * pl * F::es(w);
+        }
+    };
+    // u: [ny][2][pitch] (row records) or [2][ny][pitch]
+    auto uwhere = [&](int r, int c, uint32_t& vo, uint32_t& so) {
+        vo = (uint32_t)((RR ? 2 * r : r) * P + x) * 8u;
+        so = (uint32_t)c * (RR ? P : pl) * 8u;
+    };
+    auto load = [&](int r, Row<FMT>& R) {
+#pragma unroll
+        for (int w = 0; w < F::NW; w++) {
+            __amdgpu_buffer_rsrc_t rs;
+            uint32_t vo, so;
+            where(a.fs, ps, r, w, rs, vo, so);
+            if (F::es(w) == 8) R.w[w] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
+            else if (F::es(w) == 4) R.w[w] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
+            else R.w[w] = __builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, 0);
+        }
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            uint32_t vo, so;
+            uwhere(r, c, vo, so);
+            R.u[c] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(us, vo, so, 0));
+        }
     };
     auto store = [&](int r, const Row<FMT>& R) {
-        const uint32_t node = (uint32_t)(r * a.pitch + x);
-        if constexpr (FMT == 1) {
 #pragma unroll
-            for (int w = 0; w < 4; w++)
-                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)R.w[w], d0, node * 4u, (uint32_t)w * pl * 4u, 2);
-            __builtin_amdgcn_raw_buffer_store_b16((unsigned short)R.w[4], d1, node * 2u, 0u, 2);
-        } else if constexpr (FMT == 0) {
-#pragma unroll
-            for (int q = 0; q < 9; q++)
-                __builtin_amdgcn_raw_buffer_store_b32((uint32_t)R.w[q], q < 3 ? d0 : (q < 6 ? d1 : d2), node * 4u,
-                                                      (uint32_t)(q % 3) * pl * 4u, 2);
-        } else {
-#pragma unroll
-            for (int q = 0; q < 9; q++)
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.w[q]),
-                                                      q < 3 ? d0 : (q < 6 ? d1 : d2), node * 8u,
-                                                      (uint32_t)(q % 3) * pl * 8u, 2);
+        for (int w = 0; w < F::NW; w++) {
+            __amdgpu_buffer_rsrc_t rs;
+            uint32_t vo, so;
+            where(a.fd, pd, r, w, rs, vo, so);
+            if (F::es(w) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.w[w]), rs, vo, so, 2);
+            else if (F::es(w) == 4) __builtin_amdgcn_raw_buffer_store_b32((uint32_t)R.w[w], rs, vo, so, 2);
+            else __builtin_amdgcn_raw_buffer_store_b16((unsigned short)R.w[w], rs, vo, so, 2);
         }
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.u[0]), ud, node * 8u, 0u, 2);
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.u[1]), ud, node * 8u, pl * 8u, 2);
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            uint32_t vo, so;
+            uwhere(r, c, vo, so);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.u[c]), ud, vo, so, 2);
+        }
     };
     // two rows of loads in flight ahead of the row stored
     Row<FMT> A, B, C;
@@ -142,73 +165,81 @@ __global__ __launch_bounds__(256) void probe(Args a) {
     }
 }
 
+template <int FMT, bool RR>
+static void run(const char* name, char* f0, char* f1, char* u0, char* u1, int nx, int ny, hipEvent_t e0,
+                hipEvent_t e1) {
+    const int pitch = (nx + 63) / 64 * 64;
+    const long long plane = (long long)ny * pitch;
+    const double bpn = FMT == 0 ? 104 : (FMT == 1 ? 68 : 176);
+    CK(hipFuncSetAttribute((const void*)probe<FMT, RR>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
+    for (int chunk : {34, 64}) {
+        for (int lds : {64 << 10, 96 << 10}) {
+            Args a{f0, f1, u0, u1, nx, ny, pitch, pitch / 64, (ny + chunk - 1) / chunk, chunk, plane};
+            const int items = a.nstrip * a.nchunk, blocks = (items + 3) / 4;
+            // host check of the grid against the buffers: the last node any wave
+            // touches lies in them, and every item has a wave
+            const long long last = (long long)(ny - 1) * pitch + (pitch - 1);
+            if (last >= plane || (long long)blocks * 4 < items) {
+                std::fprintf(stderr, "bad grid\n");
+                std::exit(1);
+            }
+            auto launch = [&](int k) {
+                Args b = a;
+                if (k & 1) {
+                    b.fs = f1;
+                    b.fd = f0;
+                    b.us = u1;
+                    b.ud = u0;
+                }
+                hipLaunchKernelGGL((probe<FMT, RR>), dim3(blocks), dim3(256), lds, 0, b);
+            };
+            for (int k = 0; k < 4; k++) launch(k);
+            CK(hipDeviceSynchronize());
+            const int reps = 20;
+            CK(hipEventRecord(e0));
+            for (int k = 0; k < reps; k++) launch(k);
+            CK(hipEventRecord(e1));
+            CK(hipEventSynchronize(e1));
+            CK(hipGetLastError());
+            float ms = 0;
+            CK(hipEventElapsedTime(&ms, e0, e1));
+            const double per = ms / reps;
+            std::printf("{\"format\": \"%s\", \"layout\": \"%s\", \"chunk\": %d, \"waves_per_simd\": %d, "
+                        "\"ms\": %.4f, \"TBps_compulsory\": %.3f}\n",
+                        name, RR ? "row_records" : "planar", chunk, lds == (64 << 10) ? 2 : 1, per,
+                        bpn * nx * ny / (per * 1e-3) / 1e12);
+            std::fflush(stdout);
+        }
+    }
+}
+
 int main(int argc, char** argv) {
     const int n = argc > 1 ? std::atoi(argv[1]) : 8192;
     const int nx = n, ny = n, pitch = (nx + 63) / 64 * 64;
     const long long plane = (long long)ny * pitch;
-    if (plane * 9 * 8 / 3 >= (1ll << 32) || plane * 16 >= (1ll << 32)) {
+    // 32-bit ranges: the planar layout's three FP64 planes, and a u buffer
+    if (plane * 24 >= (1ll << 32) || plane * 16 >= (1ll << 32)) {
         std::fprintf(stderr, "lattice too large for 32-bit offsets\n");
         return 1;
     }
-    const size_t fbytes = (size_t)plane * 9 * 8, ubytes = (size_t)plane * 2 * 8;
-    char *f0, *f1;
-    double *u0, *u1;
+    const size_t fbytes = (size_t)plane * 72, ubytes = (size_t)plane * 16;
+    char *f0, *f1, *u0, *u1;
     CK(hipMalloc(&f0, fbytes));
     CK(hipMalloc(&f1, fbytes));
     CK(hipMalloc(&u0, ubytes));
     CK(hipMalloc(&u1, ubytes));
     CK(hipMemset(f0, 1, fbytes));
+    CK(hipMemset(f1, 1, fbytes));
     CK(hipMemset(u0, 0, ubytes));
-    CK(hipFuncSetAttribute((const void*)probe<0>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
-    CK(hipFuncSetAttribute((const void*)probe<1>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
-    CK(hipFuncSetAttribute((const void*)probe<2>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
+    CK(hipMemset(u1, 0, ubytes));
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    const int fmts[3] = {0, 1, 2};
-    const double bpn[3] = {104, 68, 176};
-    const char* names[3] = {"fp32", "16bit", "fp64"};
-    for (int fi = 0; fi < 3; fi++) {
-        const int fmt = fmts[fi];
-        for (int chunk : {34, 64}) {
-            for (int lds : {64 << 10, 96 << 10}) {
-                Args a{f0, f1, u0, u1, nx, ny, pitch, pitch / 64, (ny + chunk - 1) / chunk, chunk, plane};
-                const int items = a.nstrip * a.nchunk, blocks = (items + 3) / 4;
-                // host check of the grid against the buffers: the last node any wave touches
-                const long long last = (long long)(ny - 1) * pitch + (pitch - 1);
-                if (last >= plane || (long long)blocks * 4 < items) {
-                    std::fprintf(stderr, "bad grid\n");
-                    return 1;
-                }
-                auto launch = [&](int k) {
-                    Args b = a;
-                    if (k & 1) {
-                        b.fs = f1;
-                        b.fd = f0;
-                        b.us = u1;
-                        b.ud = u0;
-                    }
-                    if (fmt == 0) hipLaunchKernelGGL(probe<0>, dim3(blocks), dim3(256), lds, 0, b);
-                    else if (fmt == 1) hipLaunchKernelGGL(probe<1>, dim3(blocks), dim3(256), lds, 0, b);
-                    else hipLaunchKernelGGL(probe<2>, dim3(blocks), dim3(256), lds, 0, b);
-                };
-                for (int k = 0; k < 4; k++) launch(k);
-                CK(hipDeviceSynchronize());
-                const int reps = 20;
-                CK(hipEventRecord(e0));
-                for (int k = 0; k < reps; k++) launch(k);
-                CK(hipEventRecord(e1));
-                CK(hipEventSynchronize(e1));
-                CK(hipGetLastError());
-                float ms = 0;
-                CK(hipEventElapsedTime(&ms, e0, e1));
-                const double per = ms / reps;
-                std::printf("{\"format\": \"%s\", \"chunk\": %d, \"waves_per_simd\": %d, \"ms\": %.4f, "
-                            "\"TBps_compulsory\": %.3f}\n",
-                            names[fi], chunk, lds == (64 << 10) ? 2 : 1, per, bpn[fi] * nx * ny / (per * 1e-3) / 1e12);
-                std::fflush(stdout);
-            }
-        }
-    }
+    run<0, true>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<0, false>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<1, true>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<1, false>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<2, true>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<2, false>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
     return 0;
 }

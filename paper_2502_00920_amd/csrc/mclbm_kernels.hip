@@ -1469,14 +1469,16 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 
 // Waves per launch of march_kernel to aim for, by population storage.  Longer
 // chunks prime fewer rows, more waves balance the tail.  On the 8192^2 lattice:
-//   FP32 (2048 resident waves): 16384 waves (64-row chunks) gave 47.3k MLUPS;
-//         12288 / 20480 / 24576 / 32768 gave 4 %, 1 %, 4 % and 2 % less;
-//   FP64 (1024 resident waves): 32768 (34 rows) gave 28.4k; 12288 / 16384 / 24576 /
-//         49152 / 65536 gave 4 %, 3 %, 1.5 %, 1 % and 3 % less;
-//   FP16, BF16: 32768 (34 rows) gave 69.1k / 69.5k; 16384 and 49152 gave 1 % less.
+//   FP32 (2048 resident waves): 40960 waves (28-row chunks) gave 49.5k MLUPS;
+//         8192 / 12288 / 16384 / 32768 gave 5 %, 4.5 %, 2 % and 0.3 % less,
+//         49152 and 65536 the same;
+//   FP64 (1024 resident waves): 32768 (34 rows) gave 29.5k; 16384 / 24576 / 49152
+//         gave 0.6 %, 0.2 % and 0.6 % less;
+//   FP16, BF16: 16384 (64 rows) gave 71.8k / 72.0k; 8192 / 12288 / 32768 gave
+//         2 %, 3 % and 0.7 % less.
 template <int PR>
 constexpr long march_waves() {
-    return PR == PREC_F32 ? 16384 : 32768;
+    return PR == PREC_F32 ? 40960 : (PR == PREC_F64 ? 32768 : 16384);
 }
 
 // rows per chunk of march_kernel: a multiple of its iterations per loop trip
