@@ -1307,11 +1307,13 @@ union StepLds {
 };
 
 // The step of one lattice: one work item per wave.  FUSED (FP32 and FP64
-// only): the launch also carries the wall segments, blocks [0, nwall) (nwall a
-// multiple of 8, so the march blocks after them keep their XCD order), which
-// update the nodes on non-periodic sides; else those nodes are left to
-// wall_kernel, launched after.  Both kinds of block read only level n.  (In the
-// 16-bit formats the fused kernel spilled, inlined or not, and ran 25 %
+// only): the launch also carries the wall segments, its last nwall blocks,
+// which update the nodes on non-periodic sides; else those nodes are left to
+// wall_kernel, launched after.  Both kinds of block read only level n.  Last,
+// the wall blocks take the slots the march's final round leaves idle: first,
+// they held every slot at the march's start (walls last: 8192^2 tension +0.7 %
+// in FP32; 2048 x 128 +8 % in FP32 and FP64; 1024^2 +1 % and +4 %).  (In the
+// 16-bit formats the fused kernel spills, inlined or not, and ran 25 %
 // slower at 8192^2 and at 2048^2.)  Two waves per SIMD, but one in FP64:
 // its loop needs about 306 registers, and at two waves (256 each) the 50
 // spilled to scratch cost more than the halved occupancy (8192^2 tension:
@@ -1321,19 +1323,20 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
                                                                              int nchunk, int chunk) {
     using Lds = typename std::conditional<FUSED, StepLds<PR, HR>, HaloOf<PR, HR>[4]>::type;
     __shared__ Lds lds;
+    const int nmarch = (int)gridDim.x - nwall;  // march blocks, then wall blocks
     if constexpr (FUSED) {
-        if ((int)blockIdx.x < nwall) {
-            if ((int)blockIdx.x < wall_segs(a.g).total) {
+        if ((int)blockIdx.x >= nmarch) {
+            const int seg = (int)blockIdx.x - nmarch;
+            if (seg < wall_segs(a.g).total) {
                 const StepArgs la = a;  // a local copy: the argument block itself stays unaddressed
-                wall_segment<PR, MAT>(la, blockIdx.x, lds.band);
+                wall_segment<PR, MAT>(la, seg, lds.band);
             }
             return;
         }
     }
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int b = (int)blockIdx.x - nwall;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(b, (int)gridDim.x - nwall) * 4 + wv);
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile((int)blockIdx.x, nmarch) * 4 + wv);
     if (item >= nstrip * nchunk) return;
     if constexpr (FUSED) march_item<PR, MAT, HR, D>(a, lds.halo[wv], lane, item % nstrip, item / nstrip, chunk);
     else march_item<PR, MAT, HR, D>(a, lds[wv], lane, item % nstrip, item / nstrip, chunk);
@@ -1500,7 +1503,7 @@ static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
     const int blocks = (nstrip * nchunk + 3) / 4;
     if constexpr (PR == PREC_F32 || PR == PREC_F64) {
         if (fused) {
-            const int nwall = (wall_segs(a.g).total + 7) / 8 * 8;
+            const int nwall = wall_segs(a.g).total;
             hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, true>), dim3(nwall + blocks), dim3(256), 0, st, a,
                                nwall, nstrip, nchunk, chunk);
             return;
@@ -1515,8 +1518,8 @@ static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
 // steps, fused against two launches: FP32 gains at every size (tension32 and
 // shear128 1.8-1.9x, 2048 x 128 +49 %, 1024^2 +19 %, 2048^2 +5 %, 4096^2
 // +3 %, 8192^2 +0.7 %); FP64 gains while its march takes few blocks (1024^2,
-// 1024 blocks: +10 %) and loses 1-1.5 % from 2048^2 (4096 blocks) up; the
-// 16-bit formats lose everywhere.
+// 1024 blocks: +10 %) and loses 1-1.5 % from 2048^2 (4096 blocks) up (2 %
+// at 8192^2 with the wall blocks last); the 16-bit formats lose everywhere.
 constexpr long kFuseBlocksF64 = 2048;
 bool step_fused(int prec, const Geometry& g) {
     if (wall_segs(g).total == 0) return false;
