@@ -6,10 +6,11 @@
 // flight, on the same block-to-XCD order as march_kernel.
 //   Formats: FP32 (nine 32-bit populations), 16-bit (four 32-bit words and one
 //   16-bit value, the FP16 and BF16 layout), FP64 (nine 64-bit populations).
-//   Layouts: row records, [ny][component][pitch] (the state's layout: one
-//   buffer resource per lattice row of populations), and planar,
-//   [component][ny][pitch] (one plane per component; three planes, or the four
-//   word planes, per resource).
+//   Layouts: row records, [ny][component][pitch] (the state's layout), with a
+//   buffer resource per lattice row of populations (as march_kernel) or one
+//   per chunk, the row in the lane offset; and planar, [component][ny][pitch]
+//   (one plane per component; three planes, or the four word planes, per
+//   resource).
 //   Chunks of 34 and 64 rows; two or one waves per SIMD (set with 64 or 96 KiB
 //   of dynamic LDS per block).
 // Prints one JSON line per case: the mean launch time over 20 launches and the
@@ -63,7 +64,8 @@ struct Row {
     double u[2];
 };
 
-template <int FMT, bool RR>
+// MODE 0: planar; 1: row records, a resource per row; 2: row records, a resource per chunk
+template <int FMT, int MODE>
 __global__ __launch_bounds__(256) void probe(Args a) {
     using F = Fmt<FMT>;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -74,7 +76,11 @@ __global__ __launch_bounds__(256) void probe(Args a) {
     const int yc = chk * a.chunk, ye = min(yc + a.chunk, a.ny);
     const int y0 = max(yc - 2, 0);
     const uint32_t P = (uint32_t)a.pitch, pl = (uint32_t)a.plane;
+    constexpr bool RR = MODE != 0;
     const uint32_t rec = F::node_bytes * P;  // one lattice row's record of populations
+    // MODE 2: the chunk's rows y0 .. ye - 1 through one resource per buffer
+    const __amdgpu_buffer_rsrc_t cs = rsrc(a.fs + (size_t)y0 * rec, (uint32_t)(ye - y0) * rec),
+                                 cd = rsrc(a.fd + (size_t)y0 * rec, (uint32_t)(ye - y0) * rec);
     // planar: resources of three planes (FP32, FP64) or of the word planes and the 16-bit plane
     __amdgpu_buffer_rsrc_t ps[3], pd[3];
     if (!RR) {
@@ -95,7 +101,11 @@ __global__ __launch_bounds__(256) void probe(Args a) {
     // word w of row r: the resource, the lane's offset and the wave's offset
     auto where = [&](const char* base, const __amdgpu_buffer_rsrc_t* pr, int r, int w, __amdgpu_buffer_rsrc_t& rs,
                      uint32_t& vo, uint32_t& so) {
-        if (RR) {
+        if (MODE == 2) {
+            rs = base == a.fs ? cs : cd;
+            vo = (uint32_t)(r - y0) * rec + (uint32_t)x * F::es(w);
+            so = FMT == 1 ? (uint32_t)w * 4u * P : (uint32_t)w * F::es(w) * P;
+        } else if (RR) {
             rs = rsrc(base + (size_t)r * rec, rec);
             vo = (uint32_t)x * F::es(w);
             so = FMT == 1 ? (uint32_t)w * 4u * P : (uint32_t)w * F::es(w) * P;
@@ -165,13 +175,13 @@ __global__ __launch_bounds__(256) void probe(Args a) {
     }
 }
 
-template <int FMT, bool RR>
+template <int FMT, int MODE>
 static void run(const char* name, char* f0, char* f1, char* u0, char* u1, int nx, int ny, hipEvent_t e0,
                 hipEvent_t e1) {
     const int pitch = (nx + 63) / 64 * 64;
     const long long plane = (long long)ny * pitch;
     const double bpn = FMT == 0 ? 104 : (FMT == 1 ? 68 : 176);
-    CK(hipFuncSetAttribute((const void*)probe<FMT, RR>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
+    CK(hipFuncSetAttribute((const void*)probe<FMT, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
     for (int chunk : {34, 64}) {
         for (int lds : {64 << 10, 96 << 10}) {
             Args a{f0, f1, u0, u1, nx, ny, pitch, pitch / 64, (ny + chunk - 1) / chunk, chunk, plane};
@@ -191,7 +201,7 @@ static void run(const char* name, char* f0, char* f1, char* u0, char* u1, int nx
                     b.us = u1;
                     b.ud = u0;
                 }
-                hipLaunchKernelGGL((probe<FMT, RR>), dim3(blocks), dim3(256), lds, 0, b);
+                hipLaunchKernelGGL((probe<FMT, MODE>), dim3(blocks), dim3(256), lds, 0, b);
             };
             for (int k = 0; k < 4; k++) launch(k);
             CK(hipDeviceSynchronize());
@@ -206,7 +216,7 @@ static void run(const char* name, char* f0, char* f1, char* u0, char* u1, int nx
             const double per = ms / reps;
             std::printf("{\"format\": \"%s\", \"layout\": \"%s\", \"chunk\": %d, \"waves_per_simd\": %d, "
                         "\"ms\": %.4f, \"TBps_compulsory\": %.3f}\n",
-                        name, RR ? "row_records" : "planar", chunk, lds == (64 << 10) ? 2 : 1, per,
+                        name, MODE == 2 ? "row_records_chunk" : (MODE == 1 ? "row_records" : "planar"), chunk, lds == (64 << 10) ? 2 : 1, per,
                         bpn * nx * ny / (per * 1e-3) / 1e12);
             std::fflush(stdout);
         }
@@ -235,11 +245,14 @@ int main(int argc, char** argv) {
     hipEvent_t e0, e1;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
-    run<0, true>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
-    run<0, false>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
-    run<1, true>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
-    run<1, false>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
-    run<2, true>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
-    run<2, false>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<0, 1>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<0, 2>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<0, 0>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<1, 1>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<1, 2>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<1, 0>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<2, 1>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<2, 2>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<2, 0>("fp64", f0, f1, u0, u1, nx, ny, e0, e1);
     return 0;
 }
