@@ -5,7 +5,10 @@
 // FP64 u values and writing them to the other buffer, with two rows of loads in
 // flight, on the same block-to-XCD order as march_kernel.
 //   Formats: FP32 (nine 32-bit populations), 16-bit (four 32-bit words and one
-//   16-bit value, the FP16 and BF16 layout), FP64 (nine 64-bit populations).
+//   16-bit value, the FP16 and BF16 layout), FP64 (nine 64-bit populations), and
+//   two wider forms of FP32 in row records: pairs (four 64-bit words of two
+//   populations and one 32-bit value) and fours (two 128-bit words and one
+//   32-bit value), the same 36 B per node in fewer, wider accesses.
 //   Layouts: row records, [ny][component][pitch] (the state's layout), with a
 //   buffer resource per lattice row of populations (as march_kernel) or one
 //   per chunk, the row in the lane offset; and planar, [component][ny][pitch]
@@ -51,22 +54,27 @@ struct Args {
     long long plane;
 };
 
-// FMT 0: FP32, 1: 16-bit, 2: FP64
+// FMT 0: FP32, 1: 16-bit, 2: FP64, 3: FP32 in pairs, 4: FP32 in fours
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <int FMT>
 struct Fmt {
-    static constexpr int NW = FMT == 1 ? 5 : 9;                               // words per node
-    static constexpr uint32_t node_bytes = FMT == 0 ? 36 : (FMT == 1 ? 18 : 72);
-    __host__ __device__ static constexpr uint32_t es(int w) { return FMT == 0 ? 4 : (FMT == 1 ? (w < 4 ? 4 : 2) : 8); }
+    static constexpr int NW = FMT == 1 ? 5 : (FMT == 3 ? 5 : (FMT == 4 ? 3 : 9));  // words per node
+    static constexpr uint32_t node_bytes = (FMT == 0 || FMT >= 3) ? 36 : (FMT == 1 ? 18 : 72);
+    static constexpr bool packed = FMT == 1 || FMT >= 3;
+    __host__ __device__ static constexpr uint32_t es(int w) {
+        return FMT == 0 ? 4 : (FMT == 1 ? (w < 4 ? 4 : 2) : (FMT == 3 ? (w < 4 ? 8 : 4) : (FMT == 4 ? (w < 2 ? 16 : 4) : 8)));
+    }
 };
 template <int FMT>
 struct Row {
-    uint64_t w[Fmt<FMT>::NW];
+    u32x4 w[Fmt<FMT>::NW];
     double u[2];
 };
 
 // MODE 0: planar; 1: row records, a resource per row; 2: row records, a resource per chunk
 template <int FMT, int MODE>
 __global__ __launch_bounds__(256) void probe(Args a) {
+    static_assert(FMT < 3 || MODE != 0, "the wider FP32 forms are row records only");
     using F = Fmt<FMT>;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, gridDim.x) * 4 + wv);
@@ -104,11 +112,11 @@ __global__ __launch_bounds__(256) void probe(Args a) {
         if (MODE == 2) {
             rs = base == a.fs ? cs : cd;
             vo = (uint32_t)(r - y0) * rec + (uint32_t)x * F::es(w);
-            so = FMT == 1 ? (uint32_t)w * 4u * P : (uint32_t)w * F::es(w) * P;
+            so = F::packed ? (uint32_t)w * F::es(0) * P : (uint32_t)w * F::es(w) * P;
         } else if (RR) {
             rs = rsrc(base + (size_t)r * rec, rec);
             vo = (uint32_t)x * F::es(w);
-            so = FMT == 1 ? (uint32_t)w * 4u * P : (uint32_t)w * F::es(w) * P;
+            so = F::packed ? (uint32_t)w * F::es(0) * P : (uint32_t)w * F::es(w) * P;
         } else if (FMT == 1) {
             rs = pr[w < 4 ? 0 : 2];
             vo = (uint32_t)(r * P + x) * F::es(w);
@@ -130,9 +138,10 @@ __global__ __launch_bounds__(256) void probe(Args a) {
             __amdgpu_buffer_rsrc_t rs;
             uint32_t vo, so;
             where(a.fs, ps, r, w, rs, vo, so);
-            if (F::es(w) == 8) R.w[w] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0));
-            else if (F::es(w) == 4) R.w[w] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
-            else R.w[w] = __builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, 0);
+            if (F::es(w) == 16) R.w[w] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, vo, so, 0));
+            else if (F::es(w) == 8) { const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(rs, vo, so, 0); R.w[w].x = v.x; R.w[w].y = v.y; }
+            else if (F::es(w) == 4) R.w[w].x = __builtin_amdgcn_raw_buffer_load_b32(rs, vo, so, 0);
+            else R.w[w].x = __builtin_amdgcn_raw_buffer_load_b16(rs, vo, so, 0);
         }
 #pragma unroll
         for (int c = 0; c < 2; c++) {
@@ -147,9 +156,10 @@ __global__ __launch_bounds__(256) void probe(Args a) {
             __amdgpu_buffer_rsrc_t rs;
             uint32_t vo, so;
             where(a.fd, pd, r, w, rs, vo, so);
-            if (F::es(w) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, R.w[w]), rs, vo, so, 2);
-            else if (F::es(w) == 4) __builtin_amdgcn_raw_buffer_store_b32((uint32_t)R.w[w], rs, vo, so, 2);
-            else __builtin_amdgcn_raw_buffer_store_b16((unsigned short)R.w[w], rs, vo, so, 2);
+            if (F::es(w) == 16) __builtin_amdgcn_raw_buffer_store_b128(R.w[w], rs, vo, so, 2);
+            else if (F::es(w) == 8) { u32x2 v; v.x = R.w[w].x; v.y = R.w[w].y; __builtin_amdgcn_raw_buffer_store_b64(v, rs, vo, so, 2); }
+            else if (F::es(w) == 4) __builtin_amdgcn_raw_buffer_store_b32(R.w[w].x, rs, vo, so, 2);
+            else __builtin_amdgcn_raw_buffer_store_b16((unsigned short)R.w[w].x, rs, vo, so, 2);
         }
 #pragma unroll
         for (int c = 0; c < 2; c++) {
@@ -180,7 +190,7 @@ static void run(const char* name, char* f0, char* f1, char* u0, char* u1, int nx
                 hipEvent_t e1) {
     const int pitch = (nx + 63) / 64 * 64;
     const long long plane = (long long)ny * pitch;
-    const double bpn = FMT == 0 ? 104 : (FMT == 1 ? 68 : 176);
+    const double bpn = (FMT == 0 || FMT >= 3) ? 104 : (FMT == 1 ? 68 : 176);
     CK(hipFuncSetAttribute((const void*)probe<FMT, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 << 10));
     for (int chunk : {34, 64}) {
         for (int lds : {64 << 10, 96 << 10}) {
@@ -248,6 +258,10 @@ int main(int argc, char** argv) {
     run<0, 1>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
     run<0, 2>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
     run<0, 0>("fp32", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<3, 1>("fp32_pairs", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<3, 2>("fp32_pairs", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<4, 1>("fp32_quads", f0, f1, u0, u1, nx, ny, e0, e1);
+    run<4, 2>("fp32_quads", f0, f1, u0, u1, nx, ny, e0, e1);
     run<1, 1>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
     run<1, 2>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
     run<1, 0>("16bit", f0, f1, u0, u1, nx, ny, e0, e1);
