@@ -217,9 +217,11 @@ typedef struct mclbm_sim mclbm_sim; /* opaque host-side handle */
  * and the derived time step dt (any output pointer may be NULL).  Host only;
  * validates the parameters.  Returns EINVAL for nx or ny < 3, dx, rho0 or
  * mu <= 0, tau <= 0.5, nu outside (-1, 0.5), unknown enums or option values,
- * reserved_ != 0, or a lattice of 2^28 nodes or more once nx is rounded up to
+ * reserved_ != 0, a lattice of 2^28 nodes or more once nx is rounded up to
  * a multiple of 64 (the device addresses a displacement buffer, 16 bytes per
- * node, through one 32-bit range; about 16320^2 is the largest square). */
+ * node, through one 32-bit range; about 16320^2 is the largest square), or a
+ * rounded-up nx of 2^32 / 72 or more (one lattice row's populations, at most
+ * 72 bytes per node, through another). */
 int mclbm_plan(const mclbm_params* p, size_t* arena_bytes, size_t* align, double* dt_out);
 
 /* Create a simulation on the current HIP device inside the caller's arena

@@ -104,6 +104,12 @@ int check_params(const mclbm_params* p) {
         if (plane * 2 * 8 >= ((int64_t)1 << 32))
             return fail(MCLBM_EINVAL, "lattice of %d x %d nodes too large for one device buffer range "
                         "(a displacement buffer must stay below 4 GiB)", p->nx, p->ny);
+        // and one lattice row's record of populations (nine FP64 rows at most)
+        // through another
+        const int64_t pitch = (p->nx + 63) / 64 * 64;
+        if (pitch * 9 * 8 >= ((int64_t)1 << 32))
+            return fail(MCLBM_EINVAL, "lattice rows of %d nodes too long for one device buffer range "
+                        "(a row of populations must stay below 4 GiB)", p->nx);
     }
     if (!(p->dx > 0) || !(p->rho0 > 0) || !(p->mu > 0))
         return fail(MCLBM_EINVAL, "dx, rho0 and mu must be positive");

@@ -76,6 +76,17 @@ def test_plan_validation(M):
             with pytest.raises(M.MclbmError) as e:
                 M.mclbm_plan(p)
             assert e.value.code == M.MCLBM_EINVAL
+    # and one lattice row's record of populations (at most 72 B per node of the
+    # pitched row) must stay below 4 GiB: a long, short lattice within the
+    # displacement bound
+    for nx, ok in ((59_652_288, True), (59_652_352, False)):
+        p = M.make_params(nx, 3, mu=0.05, nu=0.3, tau=0.55, precision="f16")
+        if ok:
+            assert M.mclbm_plan(p)[0] > 0
+        else:
+            with pytest.raises(M.MclbmError) as e:
+                M.mclbm_plan(p)
+            assert e.value.code == M.MCLBM_EINVAL
     p = M.make_params(32, 32, mu=0.05, nu=0.3, tau=1.0)
     p.material = 7
     with pytest.raises(M.MclbmError):
