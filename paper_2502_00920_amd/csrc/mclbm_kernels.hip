@@ -1488,8 +1488,10 @@ hipError_t launch_nanscan(const ScanEntry* tab, int n, uint32_t* flags, hipStrea
 
 // ---- launchers ---------------------------------------------------------------------------------
 
-// Waves per launch of march_kernel to aim for, by population storage.  Longer
-// chunks prime fewer rows, more waves balance the tail.  On the 8192^2 lattice:
+// Waves per launch of march_kernel to aim for, by population storage (on large
+// FP32 and FP64 lattices march_rows aims for more).  Longer chunks prime fewer
+// rows, more waves balance the tail.  On the 8192^2 lattice (before the
+// large-lattice rule):
 //   FP32 (2048 resident waves): 40960 waves (28-row chunks) gave 49.5k MLUPS;
 //         8192 / 12288 / 16384 / 32768 gave 5 %, 4.5 %, 2 % and 0.3 % less,
 //         49152 and 65536 the same;
@@ -1512,11 +1514,29 @@ static int march_chunk(const Geometry& g, int nstrip, int L, long target) {
     return (int)(m * L - 2);
 }
 
+// Rows per chunk for one lattice: about march_waves<PR>() work items; for FP32
+// and FP64, on lattices large enough that 65536 items still give chunks of 16
+// rows or more, that many.  Measured (100 steps, MLUPS): on 8192^2, 16-row
+// chunks (65536 items) against 28 and 34: FP32 51.2k against 50.4k, FP64 29.8k
+// against 29.2k; 10-row chunks 50.2k and 29.6k.  On 4096^2 the 65536 items
+// would be 4-row chunks: FP32 38.8k against 49.4k with 10 rows, FP64 28.0k
+// against 30.8k.  FP16 and BF16 keep 64 rows (34: -0.4 %).
+constexpr long kMarchWavesLarge = 65536;
+constexpr int kMarchRowsLarge = 16;
+template <int PR>
+static int march_rows(const Geometry& g, int nstrip, int L) {
+    if constexpr (PR == PREC_F32 || PR == PREC_F64) {
+        const int big = march_chunk(g, nstrip, L, kMarchWavesLarge);
+        if (big >= kMarchRowsLarge) return big;
+    }
+    return march_chunk(g, nstrip, L, march_waves<PR>());
+}
+
 template <int PR, int MAT, int HR, int D>
 static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
     constexpr int L = (HR % D == 0) ? HR : (D % HR == 0 ? D : HR * D);
     const int nstrip = a.g.pitch / 64;
-    const int chunk = march_chunk(a.g, nstrip, L, march_waves<PR>());
+    const int chunk = march_rows<PR>(a.g, nstrip, L);
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
     const int blocks = (nstrip * nchunk + 3) / 4;
     if constexpr (PR == PREC_F32 || PR == PREC_F64) {
@@ -1544,7 +1564,7 @@ bool step_fused(int prec, const Geometry& g) {
     if (prec == PREC_F32) return true;
     if (prec != PREC_F64) return false;
     const int nstrip = g.pitch / 64;
-    const int chunk = march_chunk(g, nstrip, 6, march_waves<PREC_F64>());
+    const int chunk = march_rows<PREC_F64>(g, nstrip, 6);
     const long blocks = ((long)nstrip * ((g.ny + chunk - 1) / chunk) + 3) / 4;
     return blocks <= kFuseBlocksF64;
 }

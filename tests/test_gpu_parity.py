@@ -321,9 +321,9 @@ def test_neohooke_full_size(M, precision):
 
 @pytest.mark.parametrize("precision", ["f32", "f64"])
 def test_ragged_large_lattice(M, precision):
-    """8190 x 8191: the chunks of the benchmark's launch shape (28 rows in FP32,
-    34 in FP64) with a ragged last strip (62 of 64 columns) and a short last
-    chunk; every node against the oracle after 2 steps."""
+    """8190 x 8191: the chunks of the benchmark's launch shape (16 rows in FP32
+    and FP64) with a ragged last strip (62 of 64 columns) and a short last
+    chunk (15 rows); every node against the oracle after 2 steps."""
     print_case(f"ragged large lattice 8190x8191 {precision}")
     w = W.tension_large(8192, 1000)
     nx, ny = 8190, 8191
