@@ -1598,14 +1598,18 @@ hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t s
     }
 }
 
-// In a batch the other lattices supply the waves: chunks of 34 rows (or the
+// In a batch the other lattices supply the waves: chunks of 16 rows (or the
 // whole height, if less).  A step of a batch lasts about one chunk's march, so
 // shorter chunks end it sooner, at the price of the two rows that prime each
-// chunk; 34 rows gave the highest throughput on the serving mix (64: -9 %,
-// 22: even, 10: -9 %).
+// chunk, and short chunks started together keep neighbouring waves in step.
+// On the serving mix (200 requests, 1000..4000 steps) 16 rows against 34:
+// batched FP32 29.6 against 28.3 GLUPS, FP64 20.3 against 19.2, FP16 39.0
+// against 38.1, open-loop p50 0.37 s against 0.50 s and p99 0.69 s against
+// 0.84 s; 22 rows fell between.  (Before the state moved to row records, 34
+// rows had been the fastest: 64 -9 %, 22 even, 10 -9 %.)
 void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
     *nstrip = g.pitch / 64;
-    const int m = std::min(6, (g.ny + 2 + 5) / 6);
+    const int m = std::min(3, (g.ny + 2 + 5) / 6);
     *chunk = 6 * m - 2;
     *nchunk = (g.ny + *chunk - 1) / *chunk;
 }

@@ -11,7 +11,7 @@
 // wave, so a graph serves every round whose items fit its grid; a round with
 // more items captures the group's graph again on a grid at least twice as
 // large.  A step of a group lasts about as long as one work item (a march over
-// a chunk of at most 34 rows), whatever its size; the groups' steps are
+// a chunk of at most 16 rows), whatever its size; the groups' steps are
 // independent and run side by
 // side on the hardware queues, so that one group's tail overlaps another's
 // work.  Between rounds the host collects the simulations that have finished (their displacement is copied to the caller's buffer) and
