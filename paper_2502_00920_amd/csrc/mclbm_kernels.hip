@@ -1237,7 +1237,7 @@ struct WallBand {
 };
 
 template <int PR, int MAT>
-__device__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
+__device__ __forceinline__ void wall_segment(const StepArgs& a, int seg, WallBand& band) {
     const Geometry& g = a.g;
     const WallSegs ws = wall_segs(g);
     // side: 0 bottom row, 1 top row, 2 left column, 3 right column
@@ -1377,10 +1377,9 @@ __global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
 // XCDs in contiguous runs, as in march_kernel, so that neighbouring strips
 // share their halo lines in one L2.  A simulation's waves read only its own
 // buffers, so its results do not depend on its company.  No wave takes a
-// second item: nothing is carried from one item to the next.  (With the wall
-// blocks in the same launch, ahead of the march, the batched step ran 35 %
-// longer on the serving mix: its march needs about one round of resident
-// blocks, and the wall blocks' slots pushed it into a second.)
+// second item: nothing is carried from one item to the next.  FP16 and BF16
+// run this march and wall_batch_kernel as two launches; FP32 and FP64 run
+// march_wall_batch_kernel below.
 template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
     __shared__ HaloOf<PR, HR> halo_lds[4];
@@ -1401,6 +1400,55 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kerne
     if (e.skip) return;
     const int local = item - e.item0;
     march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
+}
+
+// The batched step of FP32 and FP64 tables in one launch: march_batch_kernel's
+// blocks on the first march_blocks blocks of the grid, then one block per wall
+// segment, as in the single-lattice fused step.  Both kinds read only level n.
+// Placed last, the wall blocks fill the slots the march's final round leaves
+// idle.  On the serving mix (200 requests, 1000..4000 steps) against two
+// launches: batched FP32 34.1 against 29.5 GLUPS, FP64 21.1 against 20.2,
+// open-loop p50 0.23 s against 0.37 s and p99 0.43 s against 0.69 s.  (With
+// the wall blocks ahead of the march the step ran 35 % longer: the march needs
+// about one round of resident blocks, and the wall blocks' slots pushed it
+// into a second.)  The 16-bit formats keep two launches: their fused
+// single-lattice kernel spilled.
+template <int PR, int MAT, int HR, int D>
+__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_wall_batch_kernel(
+    const BatchStep* __restrict__ step, int march_blocks) {
+    static_assert(PR == PREC_F32 || PR == PREC_F64, "the 16-bit formats run two launches");
+    __shared__ StepLds<PR, HR> lds;
+    const int nsims = step->nsims;
+    if ((int)blockIdx.x >= march_blocks) {
+        const int seg = (int)blockIdx.x - march_blocks;
+        if (seg >= step->nsegs) return;
+        int lo = 0, hi = nsims - 1;  // the last entry whose first segment is at or before seg
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (step->e[mid].seg0 <= seg) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchEntry& e = step->e[lo];
+        if (!e.skip) wall_segment<PR, MAT>(e.a, seg - e.seg0, lds.band);
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int nitems = step->nitems;
+    const int used = (nitems + 3) / 4;  // blocks that carry items
+    if ((int)blockIdx.x >= used) return;
+    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, used) * 4 + wv);
+    if (item >= nitems) return;
+    int lo = 0, hi = nsims - 1;  // the last entry whose first item is at or before item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (step->e[mid].item0 <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchEntry& e = step->e[lo];
+    if (e.skip) return;
+    const int local = item - e.item0;
+    march_item<PR, MAT, HR, D>(e.a, lds.halo[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
 }
 
 // The wall segments of every simulation in a batch table, one block each, after
@@ -1617,6 +1665,15 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
 template <int PR>
 static void batch_step_p(int material, const BatchStep* step, int march_blocks, int wall_blocks, hipStream_t st) {
     const dim3 grid(march_blocks), wgrid(wall_blocks), block(256);
+    if constexpr (PR == PREC_F32 || PR == PREC_F64) {
+        // one launch: the march blocks, then the wall blocks
+        const dim3 fgrid(march_blocks + wall_blocks);
+        if (material == MAT_SVK)
+            hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_SVK, 6, 2>), fgrid, block, 0, st, step, march_blocks);
+        else
+            hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_NH, 6, 2>), fgrid, block, 0, st, step, march_blocks);
+        return;
+    }
     if (material == MAT_SVK) {
         hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
         hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
