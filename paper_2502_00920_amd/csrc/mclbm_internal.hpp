@@ -152,9 +152,9 @@ int check_side_program(const void* spec);
 // prec: PREC_F64 / F32 / F16 / BF16.  The fused step: march_kernel over every
 // node off the non-periodic sides (launch_step), then the wall kernel for the
 // nodes on them, with the wall rules in FP64 (launch_walls; nothing for a
-// periodic lattice); or, when step_fused says so (lattices whose march takes
-// few blocks), one launch of march_kernel that carries the wall blocks too
-// (launch_step with fused set, and no launch_walls).
+// periodic lattice); or, when step_fused says so (FP32, FP16 and BF16, and FP64
+// lattices whose march takes few blocks), one launch of march_kernel that
+// carries the wall blocks too (launch_step with fused set, and no launch_walls).
 hipError_t launch_step(int prec, int material, const StepArgs& a, bool fused, hipStream_t st);
 hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st);
 bool step_fused(int prec, const Geometry& g);

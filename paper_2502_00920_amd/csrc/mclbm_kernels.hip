@@ -1224,8 +1224,9 @@ __global__ __launch_bounds__(256) void pass_step_kernel(PassArgs pa) {
 //
 // The march stores nothing at the nodes on non-periodic sides; wall blocks
 // update them in FP64 (node_update: the walls of Sect. 3.3 with T and sigma of
-// u_n, first-order boundary differences), launched after the march on the same
-// stream (wall_kernel, wall_batch_kernel).  A wall block takes a segment of
+// u_n, first-order boundary differences), in the march's launch after its
+// blocks (march_kernel's fused form, march_wall_batch_kernel) or in a launch
+// after it on the same stream (wall_kernel).  A wall block takes a segment of
 // kWallSeg nodes of one side (the rows 0 and ny - 1 of non-periodic y sides
 // whole, the columns 0 and nx - 1 of non-periodic x sides between them): it
 // computes T on the three node lines nearest the wall and sigma on the two
@@ -1324,15 +1325,16 @@ union StepLds {
     WallBand band;
 };
 
-// The step of one lattice: one work item per wave.  FUSED (FP32 and FP64
-// only): the launch also carries the wall segments, its last nwall blocks,
+// The step of one lattice: one work item per wave.  FUSED: the launch also
+// carries the wall segments, its last nwall blocks,
 // which update the nodes on non-periodic sides; else those nodes are left to
 // wall_kernel, launched after.  Both kinds of block read only level n.  Last,
 // the wall blocks take the slots the march's final round leaves idle: first,
 // they held every slot at the march's start (walls last: 8192^2 tension +0.7 %
-// in FP32; 2048 x 128 +8 % in FP32 and FP64; 1024^2 +1 % and +4 %).  (In the
-// 16-bit formats the fused kernel spills, inlined or not, and ran 25 %
-// slower at 8192^2 and at 2048^2.)  Two waves per SIMD, but one in FP64:
+// in FP32; 2048 x 128 +8 % in FP32 and FP64; 1024^2 +1 % and +4 %).  (The
+// 16-bit formats' fused kernel spilled while wall_segment was a call, and
+// ran 25 % slower; inlined, it fits 240 registers.)  Two waves per SIMD, but
+// one in FP64:
 // its loop needs about 306 registers, and at two waves (256 each) the 50
 // spilled to scratch cost more than the halved occupancy (8192^2 tension:
 // 26.9k MLUPS at two waves, 28.4k at one).
@@ -1361,62 +1363,35 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
 }
 
 // The wall segments of one lattice, one block each, after march_kernel on the
-// same stream (for lattices whose march fills the GPU many times over: fused
-// into the march's launch there, the wall blocks held their slots at the start
-// of the march, and 8192^2 tension ran the same in FP32 and 2 % slower in FP16).
+// same stream: the FP64 step of lattices whose march takes many blocks (see
+// step_fused).
 template <int PR, int MAT>
 __global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
     __shared__ WallBand band;
     wall_segment<PR, MAT>(a, blockIdx.x, band);
 }
 
-// The step of a batch of lattices of one material: one work item per wave, on
-// a grid the host sizes to cover the table's items (extra waves end at once).
-// A wave finds its simulation by bisection over the entries' first items (they
-// are in simulation order), and the blocks that carry items are dealt to the
-// XCDs in contiguous runs, as in march_kernel, so that neighbouring strips
-// share their halo lines in one L2.  A simulation's waves read only its own
-// buffers, so its results do not depend on its company.  No wave takes a
-// second item: nothing is carried from one item to the next.  FP16 and BF16
-// run this march and wall_batch_kernel as two launches; FP32 and FP64 run
-// march_wall_batch_kernel below.
-template <int PR, int MAT, int HR, int D>
-__global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_batch_kernel(const BatchStep* __restrict__ step) {
-    __shared__ HaloOf<PR, HR> halo_lds[4];
-    const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int nsims = step->nsims, nitems = step->nitems;
-    const int used = (nitems + 3) / 4;  // blocks that carry items
-    if ((int)blockIdx.x >= used) return;
-    const int item = __builtin_amdgcn_readfirstlane(xcd_tile(blockIdx.x, used) * 4 + wv);
-    if (item >= nitems) return;
-    int lo = 0, hi = nsims - 1;  // the last entry whose first item is at or before item
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (step->e[mid].item0 <= item) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchEntry& e = step->e[lo];
-    if (e.skip) return;
-    const int local = item - e.item0;
-    march_item<PR, MAT, HR, D>(e.a, halo_lds[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
-}
-
-// The batched step of FP32 and FP64 tables in one launch: march_batch_kernel's
-// blocks on the first march_blocks blocks of the grid, then one block per wall
-// segment, as in the single-lattice fused step.  Both kinds read only level n.
-// Placed last, the wall blocks fill the slots the march's final round leaves
-// idle.  On the serving mix (200 requests, 1000..4000 steps) against two
-// launches: batched FP32 34.1 against 29.5 GLUPS, FP64 21.1 against 20.2,
-// open-loop p50 0.23 s against 0.37 s and p99 0.43 s against 0.69 s.  (With
-// the wall blocks ahead of the march the step ran 35 % longer: the march needs
-// about one round of resident blocks, and the wall blocks' slots pushed it
-// into a second.)  The 16-bit formats keep two launches: their fused
-// single-lattice kernel spilled.
+// The step of a batch of lattices of one material in one launch.  Its first
+// march_blocks blocks march, one work item per wave, on a grid the host sizes
+// to cover the table's items (extra waves end at once); a wave finds its
+// simulation by bisection over the entries' first items (they are in
+// simulation order), and the blocks that carry items are dealt to the XCDs in
+// contiguous runs, as in march_kernel, so that neighbouring strips share their
+// halo lines in one L2.  The blocks after them take one wall segment each,
+// found by bisection over the entries' first segments.  Both kinds read only
+// level n.  A simulation's waves read only its own buffers, so its results do
+// not depend on its company.  No wave takes a second item: nothing is carried
+// from one item to the next.  Placed last, the wall blocks fill the slots the
+// march's final round leaves idle.  On the serving mix (200 requests,
+// 1000..4000 steps) against a march launch followed by a wall launch: batched
+// FP32 34.1 against 29.5 GLUPS, FP64 21.1 against 20.2, FP16 42.1 against
+// 39.0; open-loop p50 0.23 s against 0.37 s and p99 0.43 s against 0.69 s.
+// (With the wall blocks ahead of the march the step ran 35 % longer: the march
+// needs about one round of resident blocks, and the wall blocks' slots pushed
+// it into a second.)
 template <int PR, int MAT, int HR, int D>
 __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_wall_batch_kernel(
     const BatchStep* __restrict__ step, int march_blocks) {
-    static_assert(PR == PREC_F32 || PR == PREC_F64, "the 16-bit formats run two launches");
     __shared__ StepLds<PR, HR> lds;
     const int nsims = step->nsims;
     if ((int)blockIdx.x >= march_blocks) {
@@ -1449,25 +1424,6 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_wall_batch_
     if (e.skip) return;
     const int local = item - e.item0;
     march_item<PR, MAT, HR, D>(e.a, lds.halo[wv], lane, local % e.nstrip, local / e.nstrip, e.chunk);
-}
-
-// The wall segments of every simulation in a batch table, one block each, after
-// march_batch_kernel on the same stream, on a grid the host sizes to cover the
-// table's segments (extra blocks end at once); a block finds its simulation by
-// bisection over the entries' first segments.
-template <int PR, int MAT>
-__global__ __launch_bounds__(256) void wall_batch_kernel(const BatchStep* __restrict__ step) {
-    __shared__ WallBand band;
-    const int nsims = step->nsims, seg = blockIdx.x;
-    if (seg >= step->nsegs) return;
-    int lo = 0, hi = nsims - 1;  // the last entry whose first segment is at or before seg
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        if (step->e[mid].seg0 <= seg) lo = mid;
-        else hi = mid - 1;
-    }
-    const BatchEntry& e = step->e[lo];
-    if (!e.skip) wall_segment<PR, MAT>(e.a, seg - e.seg0, band);
 }
 
 hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st) {
@@ -1591,13 +1547,11 @@ static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
     const int chunk = march_rows<PR>(a.g, nstrip, L);
     const int nchunk = (a.g.ny + chunk - 1) / chunk;
     const int blocks = (nstrip * nchunk + 3) / 4;
-    if constexpr (PR == PREC_F32 || PR == PREC_F64) {
-        if (fused) {
-            const int nwall = wall_segs(a.g).total;
-            hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, true>), dim3(nwall + blocks), dim3(256), 0, st, a,
-                               nwall, nstrip, nchunk, chunk);
-            return;
-        }
+    if (fused) {
+        const int nwall = wall_segs(a.g).total;
+        hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, true>), dim3(nwall + blocks), dim3(256), 0, st, a, nwall,
+                           nstrip, nchunk, chunk);
+        return;
     }
     hipLaunchKernelGGL((march_kernel<PR, MAT, HR, D, false>), dim3(blocks), dim3(256), 0, st, a, 0, nstrip,
                        nchunk, chunk);
@@ -1609,12 +1563,12 @@ static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
 // shear128 1.8-1.9x, 2048 x 128 +49 %, 1024^2 +19 %, 2048^2 +5 %, 4096^2
 // +3 %, 8192^2 +0.7 %); FP64 gains while its march takes few blocks (1024^2,
 // 1024 blocks: +10 %) and loses 1-1.5 % from 2048^2 (4096 blocks) up (2 %
-// at 8192^2 with the wall blocks last); the 16-bit formats lose everywhere.
+// at 8192^2 with the wall blocks last); FP16 gains at every size (8192^2
+// +2.3 %, 2048^2 +8 %, 1024^2 +21 %).
 constexpr long kFuseBlocksF64 = 2048;
 bool step_fused(int prec, const Geometry& g) {
     if (wall_segs(g).total == 0) return false;
-    if (prec == PREC_F32) return true;
-    if (prec != PREC_F64) return false;
+    if (prec != PREC_F64) return true;
     const int nstrip = g.pitch / 64;
     const int chunk = march_rows<PREC_F64>(g, nstrip, 6);
     const long blocks = ((long)nstrip * ((g.ny + chunk - 1) / chunk) + 3) / 4;
@@ -1664,23 +1618,12 @@ void march_shape(const Geometry& g, int* nstrip, int* nchunk, int* chunk) {
 
 template <int PR>
 static void batch_step_p(int material, const BatchStep* step, int march_blocks, int wall_blocks, hipStream_t st) {
-    const dim3 grid(march_blocks), wgrid(wall_blocks), block(256);
-    if constexpr (PR == PREC_F32 || PR == PREC_F64) {
-        // one launch: the march blocks, then the wall blocks
-        const dim3 fgrid(march_blocks + wall_blocks);
-        if (material == MAT_SVK)
-            hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_SVK, 6, 2>), fgrid, block, 0, st, step, march_blocks);
-        else
-            hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_NH, 6, 2>), fgrid, block, 0, st, step, march_blocks);
-        return;
-    }
-    if (material == MAT_SVK) {
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step);
-        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_SVK>), wgrid, block, 0, st, step);
-    } else {
-        hipLaunchKernelGGL((march_batch_kernel<PR, MAT_NH, 6, 2>), grid, block, 0, st, step);
-        hipLaunchKernelGGL((wall_batch_kernel<PR, MAT_NH>), wgrid, block, 0, st, step);
-    }
+    // one launch: the march blocks, then the wall blocks
+    const dim3 grid(march_blocks + wall_blocks), block(256);
+    if (material == MAT_SVK)
+        hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_SVK, 6, 2>), grid, block, 0, st, step, march_blocks);
+    else
+        hipLaunchKernelGGL((march_wall_batch_kernel<PR, MAT_NH, 6, 2>), grid, block, 0, st, step, march_blocks);
 }
 
 hipError_t launch_batch_step(int prec, int material, const BatchStep* step, int march_blocks, int wall_blocks,
