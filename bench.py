@@ -3,10 +3,9 @@
 Workload: St. Venant-Kirchhoff uniaxial tension on an 8192 x 8192 D2Q9 lattice
 (mu = 0.05, nu = 0.3, tau = 0.55; left edge held, right edge pulled at
 3.2e-3 dx per step, top and bottom traction-free), synthetic and seeded.
-A step is one launch of march_kernel over every node (FP32, FP16, BF16: its
-wall blocks update the wall nodes in the same launch) or march_kernel followed
-by wall_kernel (FP64 at this size); inputs are resident in HBM
-before timing starts.  The headline value is MLUPS with
+A step is one launch of march_kernel over every node (its wall blocks update
+the wall nodes in the same launch); inputs are resident in HBM before timing
+starts.  The headline value is MLUPS with
 FP32 population storage (FP64 displacement); FP64 and the 16-bit storage modes
 (FP16, BF16) are reported beside it, each format's error against the FP64
 oracle on the 1024 x 1024 subrun (from the CPU-baseline leg), and a shortened

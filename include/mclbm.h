@@ -258,8 +258,8 @@ int mclbm_step(mclbm_sim* s, int64_t nsteps);
 /* Advance nsteps (1..100000) time steps as mclbm_step does, with HIP events
  * recorded on the stream before each step's launches, after its main kernel
  * and after the last step, and return the mean duration of one step (ms_step)
- * and of its main kernel (ms_main: march_kernel of the fused step, without the
- * wall kernel that follows it; the whole step for the multi-pass step), in
+ * and of its main kernel (ms_main: march_kernel, which carries the wall
+ * blocks; the whole step for the multi-pass step), in
  * milliseconds; either pointer may be NULL, not both.  Synchronises the
  * stream.  For measurement; the results equal those of mclbm_step bitwise. */
 int mclbm_step_timed(mclbm_sim* s, int64_t nsteps, double* ms_step, double* ms_main);

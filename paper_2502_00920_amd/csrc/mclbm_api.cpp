@@ -433,19 +433,17 @@ ReadArgs read_args(const mclbm_sim* s) {
     return a;
 }
 
-// one step on the stream: march_kernel, then the wall kernel (the event, when
-// set, is recorded between them), or march_kernel alone carrying the wall
-// blocks (lattices whose march takes few blocks; the event after it), or the
-// three passes of the multi-pass step.  (The wall kernel on a stream of its own
-// beside the march made the 8192^2 step 2 % slower in FP32 and halved the step
-// rate of small lattices, whose steps last tens of microseconds.)
+// one step on the stream: march_kernel carrying the wall blocks (the event,
+// when set, is recorded after it), or the three passes of the multi-pass step.
+// (The wall blocks as a kernel of their own on a second stream beside the march
+// made the 8192^2 step 2 % slower in FP32 and halved the step rate of small
+// lattices, whose steps last tens of microseconds.)
 hipError_t launch_one_step(mclbm_sim* s, hipEvent_t between = nullptr) {
     const StepArgs a = step_args(s);
     if (!s->L.multipass) {
         const bool fused = step_fused(s->p.precision, s->g);
         hipError_t e = launch_step(s->p.precision, s->p.material, a, fused, s->stream);
         if (e == hipSuccess && between) e = hipEventRecord(between, s->stream);
-        if (e == hipSuccess && !fused) e = launch_walls(s->p.precision, s->p.material, a, s->stream);
         return e;
     }
     PassArgs pa;

@@ -149,14 +149,11 @@ int set_error(int code, const char* msg);
 // validation of a side program (the checks of mclbm_set_side)
 int check_side_program(const void* spec);
 
-// prec: PREC_F64 / F32 / F16 / BF16.  The fused step: march_kernel over every
-// node off the non-periodic sides (launch_step), then the wall kernel for the
-// nodes on them, with the wall rules in FP64 (launch_walls; nothing for a
-// periodic lattice); or, when step_fused says so (FP32, FP16 and BF16, and FP64
-// lattices whose march takes few blocks), one launch of march_kernel that
-// carries the wall blocks too (launch_step with fused set, and no launch_walls).
+// prec: PREC_F64 / F32 / F16 / BF16.  The step: one launch of march_kernel
+// over every node off the non-periodic sides, carrying, when step_fused says
+// so (every lattice with a non-periodic side), the wall blocks that update the
+// nodes on them with the wall rules in FP64.
 hipError_t launch_step(int prec, int material, const StepArgs& a, bool fused, hipStream_t st);
-hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st);
 bool step_fused(int prec, const Geometry& g);
 // the multi-pass step: stresses, source, step (three launches)
 hipError_t launch_stress_pass(int material, const InitLike& b, double* T, hipStream_t st);

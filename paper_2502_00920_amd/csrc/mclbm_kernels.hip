@@ -1225,8 +1225,7 @@ __global__ __launch_bounds__(256) void pass_step_kernel(PassArgs pa) {
 // The march stores nothing at the nodes on non-periodic sides; wall blocks
 // update them in FP64 (node_update: the walls of Sect. 3.3 with T and sigma of
 // u_n, first-order boundary differences), in the march's launch after its
-// blocks (march_kernel's fused form, march_wall_batch_kernel) or in a launch
-// after it on the same stream (wall_kernel).  A wall block takes a segment of
+// blocks (march_kernel's fused form, march_wall_batch_kernel).  A wall block takes a segment of
 // kWallSeg nodes of one side (the rows 0 and ny - 1 of non-periodic y sides
 // whole, the columns 0 and nx - 1 of non-periodic x sides between them): it
 // computes T on the three node lines nearest the wall and sigma on the two
@@ -1325,10 +1324,10 @@ union StepLds {
     WallBand band;
 };
 
-// The step of one lattice: one work item per wave.  FUSED: the launch also
-// carries the wall segments, its last nwall blocks,
-// which update the nodes on non-periodic sides; else those nodes are left to
-// wall_kernel, launched after.  Both kinds of block read only level n.  Last,
+// The step of one lattice: one work item per wave.  FUSED (every lattice with
+// a non-periodic side): the launch also carries the wall segments, its last
+// nwall blocks, which update the nodes on those sides.  Both kinds of block
+// read only level n.  Last,
 // the wall blocks take the slots the march's final round leaves idle: first,
 // they held every slot at the march's start (walls last: 8192^2 tension +0.7 %
 // in FP32; 2048 x 128 +8 % in FP32 and FP64; 1024^2 +1 % and +4 %).  (The
@@ -1360,15 +1359,6 @@ __global__ __launch_bounds__(256, PR == PREC_F64 ? 1 : 2) void march_kernel(Step
     if (item >= nstrip * nchunk) return;
     if constexpr (FUSED) march_item<PR, MAT, HR, D>(a, lds.halo[wv], lane, item % nstrip, item / nstrip, chunk);
     else march_item<PR, MAT, HR, D>(a, lds[wv], lane, item % nstrip, item / nstrip, chunk);
-}
-
-// The wall segments of one lattice, one block each, after march_kernel on the
-// same stream: the FP64 step of lattices whose march takes many blocks (see
-// step_fused).
-template <int PR, int MAT>
-__global__ __launch_bounds__(256) void wall_kernel(StepArgs a) {
-    __shared__ WallBand band;
-    wall_segment<PR, MAT>(a, blockIdx.x, band);
 }
 
 // The step of a batch of lattices of one material in one launch.  Its first
@@ -1557,47 +1547,16 @@ static void launch_march(const StepArgs& a, bool fused, hipStream_t st) {
                        nchunk, chunk);
 }
 
-// Whether one lattice's step runs as one fused launch (march and wall blocks)
-// rather than march_kernel followed by wall_kernel.  Measured, back-to-back
-// steps, fused against two launches: FP32 gains at every size (tension32 and
-// shear128 1.8-1.9x, 2048 x 128 +49 %, 1024^2 +19 %, 2048^2 +5 %, 4096^2
-// +3 %, 8192^2 +0.7 %); FP64 gains while its march takes few blocks (1024^2,
-// 1024 blocks: +10 %) and loses 1-1.5 % from 2048^2 (4096 blocks) up (2 %
-// at 8192^2 with the wall blocks last); FP16 gains at every size (8192^2
-// +2.3 %, 2048^2 +8 %, 1024^2 +21 %).
-constexpr long kFuseBlocksF64 = 2048;
+// Whether one lattice's step carries wall blocks (march_kernel's fused form):
+// every lattice with a non-periodic side.  Measured, back-to-back steps,
+// against the march followed by a launch of the wall blocks alone: FP32 gains
+// at every size (tension32 and shear128 1.8-1.9x, 2048 x 128 +49 %, 1024^2
+// +19 %, 2048^2 +5 %, 4096^2 +3 %, 8192^2 +0.7 %), FP16 too (8192^2 +2.3 %,
+// 2048^2 +8 %, 1024^2 +21 %), and FP64 (1024^2 +10 %; with 16-row chunks and
+// the wall segment inlined, 2048^2 +4 %, 4096^2 +1.9 %, 8192^2 +0.5 %).
 bool step_fused(int prec, const Geometry& g) {
-    if (wall_segs(g).total == 0) return false;
-    if (prec != PREC_F64) return true;
-    const int nstrip = g.pitch / 64;
-    const int chunk = march_rows<PREC_F64>(g, nstrip, 6);
-    const long blocks = ((long)nstrip * ((g.ny + chunk - 1) / chunk) + 3) / 4;
-    return blocks <= kFuseBlocksF64;
-}
-
-template <int PR, int MAT>
-static void launch_walls_pm(const StepArgs& a, hipStream_t st) {
-    const int nseg = wall_segs(a.g).total;
-    if (nseg > 0) hipLaunchKernelGGL((wall_kernel<PR, MAT>), dim3(nseg), dim3(256), 0, st, a);
-}
-
-template <int PR>
-static hipError_t walls_p(int material, const StepArgs& a, hipStream_t st) {
-    switch (material) {
-    case MAT_SVK: launch_walls_pm<PR, MAT_SVK>(a, st); break;
-    case MAT_NH: launch_walls_pm<PR, MAT_NH>(a, st); break;
-    default: launch_walls_pm<PR, MAT_LIN>(a, st); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_walls(int prec, int material, const StepArgs& a, hipStream_t st) {
-    switch (prec) {
-    case PREC_F64: return walls_p<PREC_F64>(material, a, st);
-    case PREC_F32: return walls_p<PREC_F32>(material, a, st);
-    case PREC_F16: return walls_p<PREC_F16>(material, a, st);
-    default: return walls_p<PREC_BF16>(material, a, st);
-    }
+    (void)prec;
+    return wall_segs(g).total > 0;
 }
 
 // In a batch the other lattices supply the waves: chunks of 16 rows (or the

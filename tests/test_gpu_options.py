@@ -367,9 +367,9 @@ def test_captured_steps_replay(M, precision, n):
     the wall values of those steps), so a graph of an even number of steps under
     constant wall programs replays as the same steps run eagerly.  Each of five
     replays is checked bitwise against an eager twin, with the twin's eager steps
-    and a synchronisation between replays.  The lattices cover the step as one
-    launch (FP32, FP16, FP64 on few blocks) and as the march followed by the
-    wall kernel (FP64 on 1600 x 1600, 2500 march blocks)."""
+    and a synchronisation between replays.  The lattices cover every storage
+    format's one-launch step, on few march blocks and on many (FP64 on
+    1600 x 1600, 2500 march blocks)."""
     import torch
     print_case(f"captured steps {precision} {n}x{n}")
     st = torch.cuda.Stream()
